@@ -1,0 +1,240 @@
+/*
+ * tang.h -- C ABI of an MI355X (gfx950) batched 5-field packet classifier.
+ *
+ * The method is TaNG's two-stage classification (Sec. 5.1.1): a small MLP reads each
+ * packet header and predicts which tuple of a tuple space (Sec. 4.3) holds the answer;
+ * the packet's SIP/DIP are truncated to that tuple's prefix lengths, hashed, and the
+ * hashed bucket's rules are compared one by one. Unlike the paper, which accepts a
+ * rare lower-priority answer (Sec. 5.1.1, Sec. 8), this library certifies every
+ * answer: after the predicted tuples it probes each tuple that holds a higher-priority
+ * rule overlapping the match found (a per-rule "conflict mask"), or every remaining
+ * tuple when nothing matched. The returned id is therefore always the exact
+ * highest-priority match, whatever the model predicts.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns int: 0 on success or a negative TANG_E* code. No C++
+ *     exception crosses this boundary. tang_last_error() returns a message for the
+ *     last failure on the calling thread.
+ *   - "device pointer" means memory the caller allocated on the ruleset's GPU (for
+ *     example a torch tensor's data_ptr); "host pointer" means ordinary CPU memory.
+ *   - A stream argument is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Input arrays are deep-copied; the caller keeps ownership of everything it passes.
+ *   - The library owns only its internal device memory (hipMalloc'd on the ruleset's
+ *     device, freed by tang_ruleset_destroy).
+ */
+#ifndef TANG_H
+#define TANG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TANG_NO_MATCH 0xFFFFFFFFu /* rule_id when no rule matches (no default rule) */
+#define TANG_HOST_ONLY (-1)       /* device argument: build host structures only */
+#define TANG_MAX_TUPLES 32        /* conflict masks are 32-bit */
+#define TANG_MAX_TOPK 4
+#define TANG_MAX_LAYERS 8
+
+enum {
+    TANG_OK = 0,
+    TANG_EINVAL = -1,    /* bad argument or rule field */
+    TANG_ENOMEM = -2,    /* host or device allocation failed, or a capacity is exceeded */
+    TANG_ENOTFOUND = -3, /* delete of an id that is not live */
+    TANG_EEXIST = -4,    /* insert of an id that is already live (or repeated in a batch) */
+    TANG_EDEVICE = -5,   /* a HIP call failed */
+    TANG_EBUSY = -6,     /* server: request refused or still running */
+    TANG_ETIMEOUT = -7   /* server: wait timed out */
+};
+
+/*
+ * A rule (Sec. 2.1): SIP and DIP prefixes (value + length 0..32; bits beyond the
+ * length are ignored and normalised to zero), inclusive port ranges lo <= hi, and a
+ * protocol that is exact (proto_mask = 0xFF) or wildcard (proto_mask = 0). Priorities
+ * follow Table 1: a lower number is a higher priority. Equal priorities are ordered by
+ * the lower id. id must be unique among live rules and != TANG_NO_MATCH. 28 bytes.
+ */
+typedef struct tang_rule_s {
+    uint32_t sip, dip;
+    uint32_t priority;
+    uint32_t id;
+    uint16_t sp_lo, sp_hi, dp_lo, dp_hi;
+    uint8_t sip_len, dip_len;
+    uint8_t proto, proto_mask;
+} tang_rule_t;
+
+/* A packet header, 16 bytes (13 used): SIP, DIP, SP, DP, protocol, 3 pad bytes. */
+typedef struct tang_header_s {
+    uint32_t sip, dip;
+    uint16_t sp, dp;
+    uint8_t proto;
+    uint8_t pad[3];
+} tang_header_t;
+
+typedef enum { TANG_FP32 = 0, TANG_BF16 = 1, TANG_FP8 = 2 } tang_precision_t;
+
+/*
+ * The predictor (Sec. 6.1, plain form without residual blocks): n_layers Linear
+ * layers, dims[0] -> dims[1] -> ... -> dims[n_layers], ReLU after every layer but the
+ * last. dims[0] must be 104: the header's bits, most significant first, over SIP(32)
+ * DIP(32) SP(16) DP(16) PROTO(8), each as 0.0 or 1.0. dims[n_layers] must equal
+ * tang_ruleset_num_tuples(). Supported now: n_layers = 3 with equal hidden widths
+ * 128 or 256. topk (1..4) is how many top-scoring tuples are probed before
+ * certification; equal scores go to the lower tuple index (argmax of Sec. 6.1 for 1).
+ */
+typedef struct tang_mlp_desc_s {
+    uint32_t n_layers;
+    uint32_t dims[TANG_MAX_LAYERS + 1];
+    uint32_t topk;
+} tang_mlp_desc_t;
+
+/* Optional per-call counters (tang_classify with a non-NULL stats; synchronises). */
+typedef struct tang_stats_s {
+    uint64_t packets;     /* packets classified */
+    uint64_t probes;      /* hash-table probes (one per tuple searched) */
+    uint64_t slots;       /* hash slots read */
+    uint64_t records;     /* rule records compared */
+    uint64_t top1_hits;   /* answer lies in the first predicted tuple */
+    uint64_t fallbacks;   /* nothing matched in the predicted tuples */
+    uint64_t no_match;    /* packets with no matching rule at all */
+} tang_stats_t;
+
+typedef struct tang_ruleset_s tang_ruleset_t;
+
+/*
+ * Build a ruleset: tuple space with tuples numbered by first appearance over rules in
+ * ascending (priority, id) order (Table 1), one open-addressing hash table of buckets
+ * keyed by (tuple, SIP & mask, DIP & mask), each bucket's rules sorted by (priority,
+ * id) (Sec. 4.3, 5.1.1), and per-rule conflict masks computed on the GPU.
+ * device: GPU ordinal, or TANG_HOST_ONLY to build only the host tuple space (for
+ * inspection; such a ruleset cannot classify or load a model).
+ * rules: host pointer to n rules (n may be 0). *out receives the handle.
+ * Errors: EINVAL (a length > 32, lo > hi, proto_mask not 0/0xFF, id = TANG_NO_MATCH,
+ * more than TANG_MAX_TUPLES signatures), EEXIST (repeated id), ENOMEM, EDEVICE.
+ */
+int tang_ruleset_create(int device, const tang_rule_t* rules, size_t n, tang_ruleset_t** out);
+void tang_ruleset_destroy(tang_ruleset_t* rs);
+
+/* Number of tuples C (the model's output width) and the signature of tuple t. */
+uint32_t tang_ruleset_num_tuples(const tang_ruleset_t* rs);
+int tang_ruleset_tuple(const tang_ruleset_t* rs, uint32_t t, uint8_t* sip_len, uint8_t* dip_len);
+/* Number of live rules. */
+size_t tang_ruleset_num_rules(const tang_ruleset_t* rs);
+/* Tuple that holds live rule `id` (ENOTFOUND if none). */
+int tang_ruleset_rule_tuple(const tang_ruleset_t* rs, uint32_t id, uint32_t* tuple);
+/* Conflict mask of live rule `id`, read back from the device (synchronises). */
+int tang_ruleset_conflict_mask(tang_ruleset_t* rs, uint32_t id, uint32_t* mask);
+/* Device bytes held by the ruleset (tables, records, model). */
+int tang_ruleset_device_bytes(const tang_ruleset_t* rs, size_t* bytes);
+/* Stream on which updates are applied (default: the null stream). */
+int tang_ruleset_set_stream(tang_ruleset_t* rs, void* stream);
+
+/*
+ * Load predictor weights (deep copy). W[l] is a host pointer to dims[l+1] x dims[l]
+ * floats, row-major [out][in] (PyTorch nn.Linear.weight); b[l] to dims[l+1] floats.
+ * precision: FP32 (weights as given), BF16 (weights and each layer's input rounded to
+ * bfloat16, nearest-even), FP8 (OCP E4M3, per-layer weight scale amax|W|/448 and
+ * static per-layer activation scales act_scales[l] for l >= 1, act_scales[0] ignored
+ * since the input bits are exact; inputs saturate at +-448). Accumulation is FP32 and
+ * biases stay FP32 in every precision. act_scales must be NULL unless precision is FP8.
+ * Replaces any previously loaded model. Without a model, classify probes all tuples.
+ */
+int tang_model_load(tang_ruleset_t* rs, const tang_mlp_desc_t* desc, const float* const* W,
+                    const float* const* b, tang_precision_t precision, const float* act_scales);
+int tang_model_unload(tang_ruleset_t* rs);
+
+/*
+ * Classify n headers: d_rule_id[i] = id of the highest-priority live rule matching
+ * d_hdr[i], or TANG_NO_MATCH. d_hdr, d_rule_id: device pointers on the ruleset's GPU,
+ * caller-owned, valid until the stream has passed this work. Asynchronous on `stream`
+ * unless stats != NULL (then the counters are copied back and the call synchronises).
+ * n = 0 is a no-op. Concurrent classify calls on any streams are allowed while no
+ * update is in flight; order updates before classify through the streams.
+ */
+int tang_classify(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id,
+                  size_t n, void* stream, tang_stats_t* stats);
+/* Same with host pointers; copies in and out and synchronises. For tests and tools. */
+int tang_classify_host(tang_ruleset_t* rs, const tang_header_t* hdr, uint32_t* rule_id,
+                       size_t n, tang_stats_t* stats);
+/*
+ * The two stages of tang_classify, callable one by one (Sec. 5.1.1): tang_predict runs
+ * the model and writes each header's candidate tuples into d_io[i] (one byte per
+ * candidate, first candidate in the low byte); tang_search then probes, verifies and
+ * certifies, reading those candidates from d_io and overwriting them with the rule ids.
+ * Without a model tang_predict is an error and tang_search probes every tuple. Same
+ * buffers, stream and concurrency rules as tang_classify; tang_search's stats as there.
+ */
+int tang_predict(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_io, size_t n,
+                 void* stream);
+int tang_search(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_io, size_t n,
+                void* stream, tang_stats_t* stats);
+/*
+ * Predictor only: d_logits (device, may be NULL) receives n x C FP32 scores and d_cand
+ * (device, may be NULL) n x topk tuple indices. Asynchronous on `stream`. Needs a model.
+ */
+int tang_mlp_forward(tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n, float* d_logits,
+                     uint8_t* d_cand, void* stream);
+
+/*
+ * Immediate updates (Sec. 5.2.1). The tuple set is kept: an inserted rule goes to the
+ * tuple with its own signature, else to the first tuple with the largest length sum
+ * among those whose lengths are all <= the rule's (its prefixes are then checked in
+ * the bucket scan); only if no tuple qualifies is a new tuple appended (the model
+ * never predicts it; certification and the fallback still search it).
+ * A batch is validated as a whole before anything changes (all-or-nothing): insert
+ * fails with EEXIST on a live or repeated id and EINVAL on a bad field; delete fails
+ * with ENOTFOUND on an id that is not live. The device changes are enqueued on the
+ * ruleset's stream (tang_ruleset_set_stream); later classify calls on that stream see
+ * them. rules/ids: host pointers.
+ */
+int tang_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n);
+int tang_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n);
+
+/* Message for the calling thread's last error ("" if none). */
+const char* tang_last_error(void);
+
+/* ------------------------------------------------------------------------------------
+ * Serving loop: continuous batching over several device-resident rulesets.
+ * A persistent host thread admits submitted requests while in-flight packets and device
+ * staging bytes stay within the configured limits, packs admitted requests of the same
+ * ruleset into one batch, replays a captured HIP graph for that (ruleset, batch size
+ * class), and completes each request with submit / admit / done timestamps.
+ */
+typedef struct tang_server_cfg_s {
+    size_t mem_budget_bytes;        /* device staging bytes for in-flight batches */
+    uint32_t max_inflight_packets;  /* admission limit on packets on the GPU */
+    uint32_t n_streams;             /* concurrent batches (1..8) */
+    uint32_t max_batch;             /* packets per launched batch (power of two) */
+    uint32_t use_graphs;            /* 1: replay captured HIP graphs per size class */
+} tang_server_cfg_t;
+
+typedef struct tang_server_s tang_server_t;
+typedef struct tang_req_s tang_req_t;
+
+int tang_server_create(int device, const tang_server_cfg_t* cfg, tang_server_t** out);
+/* Register a ruleset (same device); *tag identifies it in submits. */
+int tang_server_add_ruleset(tang_server_t* srv, tang_ruleset_t* rs, uint32_t* tag);
+/*
+ * Submit n host headers for ruleset `tag`; results go to host array out[n] when the
+ * request completes. hdr and out must stay valid until then. EBUSY if the request can
+ * never be admitted (larger than the limits), EINVAL on a bad tag.
+ */
+int tang_server_submit(tang_server_t* srv, uint32_t tag, const tang_header_t* hdr, size_t n,
+                       uint32_t* out, tang_req_t** req);
+/* Wait up to timeout_us (< 0: forever). 0 when done, ETIMEOUT otherwise. */
+int tang_server_wait(tang_req_t* req, int64_t timeout_us);
+/* 1 if done, 0 if not. */
+int tang_server_poll(const tang_req_t* req);
+/* Timestamps in ns on the host steady clock: submitted, admitted, completed. */
+int tang_server_req_times(const tang_req_t* req, uint64_t* submit_ns, uint64_t* admit_ns,
+                          uint64_t* done_ns);
+void tang_server_req_free(tang_req_t* req);
+/* Drains pending work, stops the loop, frees the server (not the rulesets). */
+int tang_server_destroy(tang_server_t* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TANG_H */

@@ -1,0 +1,294 @@
+// C ABI entry points (include/tang.h): argument checks, error codes, and the calls
+// into the host tuple space and the kernels. No C++ exception crosses this boundary.
+#include <new>
+
+#include "tang_internal.hpp"
+
+namespace tang {
+
+static thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return TANG_EDEVICE;
+}
+
+}  // namespace tang
+
+using namespace tang;
+
+size_t tang_ruleset_s::device_bytes() const {
+    if (device == TANG_HOST_ONLY) return 0;
+    return slots.size() * sizeof(Slot) + (size_t)rec_cap * sizeof(Rec) + sizeof(TupleTable) +
+           sizeof(StatsDev) + model.bytes;
+}
+
+#define TANG_GUARD_BEGIN try {
+#define TANG_GUARD_END                                                   \
+    }                                                                    \
+    catch (const std::bad_alloc&) {                                      \
+        return fail(TANG_ENOMEM, "host allocation failed");              \
+    }                                                                    \
+    catch (const std::exception& ex) {                                   \
+        return fail(TANG_EINVAL, std::string("internal error: ") + ex.what()); \
+    }                                                                    \
+    catch (...) {                                                        \
+        return fail(TANG_EINVAL, "internal error");                      \
+    }
+
+static void free_device(tang_ruleset_t* rs) {
+    if (rs->device == TANG_HOST_ONLY) return;
+    hipSetDevice(rs->device);
+    model_free(rs->model);
+    if (rs->d_slots) hipFree(rs->d_slots);
+    if (rs->d_recs) hipFree(rs->d_recs);
+    if (rs->d_tt) hipFree(rs->d_tt);
+    if (rs->d_stats) hipFree(rs->d_stats);
+    rs->d_slots = nullptr;
+    rs->d_recs = nullptr;
+    rs->d_tt = nullptr;
+    rs->d_stats = nullptr;
+}
+
+extern "C" {
+
+const char* tang_last_error(void) { return tang::g_err.c_str(); }
+
+int tang_ruleset_create(int device, const tang_rule_t* rules, size_t n, tang_ruleset_t** out) {
+    TANG_GUARD_BEGIN
+    if (!out) return fail(TANG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (device != TANG_HOST_ONLY) {
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+        if (count == 0) return fail(TANG_EDEVICE, "no HIP device available");
+        if (device < 0 || device >= count) return fail(TANG_EINVAL, "bad device ordinal");
+    }
+    std::unique_ptr<tang_ruleset_t> rs(new tang_ruleset_t());
+    rs->device = device;
+    int rc = build_host(rs.get(), rules, n);
+    if (rc) return rc;
+    if (device != TANG_HOST_ONLY) {
+        rc = upload_all(rs.get());
+        if (rc) {
+            free_device(rs.get());
+            return rc;
+        }
+    }
+    *out = rs.release();
+    return TANG_OK;
+    TANG_GUARD_END
+}
+
+void tang_ruleset_destroy(tang_ruleset_t* rs) {
+    if (!rs) return;
+    free_device(rs);
+    delete rs;
+}
+
+uint32_t tang_ruleset_num_tuples(const tang_ruleset_t* rs) {
+    return rs ? (uint32_t)rs->sigs.size() : 0;
+}
+
+int tang_ruleset_tuple(const tang_ruleset_t* rs, uint32_t t, uint8_t* sip_len, uint8_t* dip_len) {
+    if (!rs || !sip_len || !dip_len) return fail(TANG_EINVAL, "NULL argument");
+    if (t >= rs->sigs.size()) return fail(TANG_EINVAL, "tuple index out of range");
+    *sip_len = rs->sigs[t].first;
+    *dip_len = rs->sigs[t].second;
+    return TANG_OK;
+}
+
+size_t tang_ruleset_num_rules(const tang_ruleset_t* rs) { return rs ? rs->n_live : 0; }
+
+int tang_ruleset_rule_tuple(const tang_ruleset_t* rs, uint32_t id, uint32_t* tuple) {
+    TANG_GUARD_BEGIN
+    if (!rs || !tuple) return fail(TANG_EINVAL, "NULL argument");
+    auto it = rs->id2h.find(id);
+    if (it == rs->id2h.end()) return fail(TANG_ENOTFOUND, "rule id is not live");
+    *tuple = rs->rules[it->second].tuple;
+    return TANG_OK;
+    TANG_GUARD_END
+}
+
+int tang_ruleset_conflict_mask(tang_ruleset_t* rs, uint32_t id, uint32_t* mask) {
+    TANG_GUARD_BEGIN
+    if (!rs || !mask) return fail(TANG_EINVAL, "NULL argument");
+    if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset has no masks");
+    auto it = rs->id2h.find(id);
+    if (it == rs->id2h.end()) return fail(TANG_ENOTFOUND, "rule id is not live");
+    TANG_HIP(hipSetDevice(rs->device));
+    Rec r;
+    TANG_HIP(hipMemcpy(&r, rs->d_recs + rs->rules[it->second].pos, sizeof r, hipMemcpyDeviceToHost));
+    if (r.id != id) return fail(TANG_EINVAL, "record/handle mismatch");
+    *mask = r.cmask;
+    return TANG_OK;
+    TANG_GUARD_END
+}
+
+int tang_ruleset_device_bytes(const tang_ruleset_t* rs, size_t* bytes) {
+    if (!rs || !bytes) return fail(TANG_EINVAL, "NULL argument");
+    *bytes = rs->device_bytes();
+    return TANG_OK;
+}
+
+int tang_ruleset_set_stream(tang_ruleset_t* rs, void* stream) {
+    if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    rs->upd_stream = (hipStream_t)stream;
+    return TANG_OK;
+}
+
+int tang_model_load(tang_ruleset_t* rs, const tang_mlp_desc_t* desc, const float* const* W,
+                    const float* const* b, tang_precision_t precision, const float* act_scales) {
+    TANG_GUARD_BEGIN
+    if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset cannot hold a model");
+    TANG_HIP(hipSetDevice(rs->device));
+    TANG_HIP(hipDeviceSynchronize());  // no classify may still read the old weights
+    return model_prepare(rs, desc, W, b, precision, act_scales);
+    TANG_GUARD_END
+}
+
+int tang_model_unload(tang_ruleset_t* rs) {
+    if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    if (rs->device != TANG_HOST_ONLY) {
+        TANG_HIP(hipSetDevice(rs->device));
+        TANG_HIP(hipDeviceSynchronize());
+    }
+    model_free(rs->model);
+    rs->version++;
+    return TANG_OK;
+}
+
+static int check_classify(const tang_ruleset_t* rs, const void* hdr, const void* out, size_t n) {
+    if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset cannot classify");
+    if (n && (!hdr || !out)) return fail(TANG_EINVAL, "NULL buffer");
+    if (((uintptr_t)hdr & 15u) != 0) return fail(TANG_EINVAL, "headers must be 16-byte aligned");
+    if (((uintptr_t)out & 3u) != 0) return fail(TANG_EINVAL, "rule_id buffer must be 4-byte aligned");
+    return TANG_OK;
+}
+
+static int run_search(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_io, size_t n,
+                      hipStream_t s, tang_stats_t* stats) {
+    std::unique_lock<std::mutex> lk(rs->stats_mu, std::defer_lock);
+    if (stats) {
+        lk.lock();
+        TANG_HIP(hipMemsetAsync(rs->d_stats, 0, sizeof(StatsDev), s));
+    }
+    const int kcand = rs->model.loaded ? rs->model.topk : 0;
+    TANG_HIP(launch_classify(rs, d_hdr, d_io, n, kcand, s, stats != nullptr));
+    if (stats) {
+        StatsDev h;
+        TANG_HIP(hipMemcpyAsync(&h, rs->d_stats, sizeof h, hipMemcpyDeviceToHost, s));
+        TANG_HIP(hipStreamSynchronize(s));
+        stats->packets = h.packets;
+        stats->probes = h.probes;
+        stats->slots = h.slots;
+        stats->records = h.records;
+        stats->top1_hits = h.top1;
+        stats->fallbacks = h.fallbacks;
+        stats->no_match = h.nomatch;
+    }
+    return TANG_OK;
+}
+
+int tang_classify(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id, size_t n,
+                  void* stream, tang_stats_t* stats) {
+    TANG_GUARD_BEGIN
+    int rc = check_classify(rs, d_hdr, d_rule_id, n);
+    if (rc) return rc;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n == 0) return TANG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    TANG_HIP(hipSetDevice(rs->device));
+    if (rs->model.loaded) TANG_HIP(launch_mlp(rs, d_hdr, n, d_rule_id, nullptr, nullptr, s));
+    return run_search(rs, d_hdr, d_rule_id, n, s, stats);
+    TANG_GUARD_END
+}
+
+int tang_predict(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_io, size_t n,
+                 void* stream) {
+    TANG_GUARD_BEGIN
+    int rc = check_classify(rs, d_hdr, d_io, n);
+    if (rc) return rc;
+    if (!rs->model.loaded) return fail(TANG_EINVAL, "no model loaded");
+    if (n == 0) return TANG_OK;
+    TANG_HIP(hipSetDevice(rs->device));
+    TANG_HIP(launch_mlp(rs, d_hdr, n, d_io, nullptr, nullptr, (hipStream_t)stream));
+    return TANG_OK;
+    TANG_GUARD_END
+}
+
+int tang_search(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_io, size_t n,
+                void* stream, tang_stats_t* stats) {
+    TANG_GUARD_BEGIN
+    int rc = check_classify(rs, d_hdr, d_io, n);
+    if (rc) return rc;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n == 0) return TANG_OK;
+    TANG_HIP(hipSetDevice(rs->device));
+    return run_search(rs, d_hdr, d_io, n, (hipStream_t)stream, stats);
+    TANG_GUARD_END
+}
+
+int tang_classify_host(tang_ruleset_t* rs, const tang_header_t* hdr, uint32_t* rule_id, size_t n,
+                       tang_stats_t* stats) {
+    TANG_GUARD_BEGIN
+    if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset cannot classify");
+    if (n && (!hdr || !rule_id)) return fail(TANG_EINVAL, "NULL buffer");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n == 0) return TANG_OK;
+    TANG_HIP(hipSetDevice(rs->device));
+    tang_header_t* dh = nullptr;
+    uint32_t* dout = nullptr;
+    TANG_HIP(hipMalloc(&dh, n * sizeof(tang_header_t)));
+    hipError_t e = hipMalloc(&dout, n * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemcpy(dh, hdr, n * sizeof(tang_header_t), hipMemcpyHostToDevice);
+    int rc = TANG_OK;
+    if (e == hipSuccess) {
+        rc = tang_classify(rs, dh, dout, n, nullptr, stats);
+        if (rc == TANG_OK) e = hipMemcpy(rule_id, dout, n * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    }
+    hipFree(dh);
+    if (dout) hipFree(dout);
+    if (e != hipSuccess) return hip_fail(e, "tang_classify_host");
+    return rc;
+    TANG_GUARD_END
+}
+
+int tang_mlp_forward(tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n, float* d_logits,
+                     uint8_t* d_cand, void* stream) {
+    TANG_GUARD_BEGIN
+    if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    if (rs->device == TANG_HOST_ONLY || !rs->model.loaded) return fail(TANG_EINVAL, "no model loaded");
+    if (n && !d_hdr) return fail(TANG_EINVAL, "NULL headers");
+    if (((uintptr_t)d_hdr & 15u) != 0) return fail(TANG_EINVAL, "headers must be 16-byte aligned");
+    if (n == 0) return TANG_OK;
+    TANG_HIP(hipSetDevice(rs->device));
+    TANG_HIP(launch_mlp(rs, d_hdr, n, nullptr, d_logits, d_cand, (hipStream_t)stream));
+    return TANG_OK;
+    TANG_GUARD_END
+}
+
+int tang_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
+    TANG_GUARD_BEGIN
+    if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    return apply_insert(rs, rules, n);
+    TANG_GUARD_END
+}
+
+int tang_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n) {
+    TANG_GUARD_BEGIN
+    if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    return apply_delete(rs, ids, n);
+    TANG_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,499 @@
+// Tuple predictor on MFMA: the plain MLP of Sec. 6.1 (FC -> ReLU -> FC -> ReLU -> FC,
+// 104 -> H -> H -> C) followed by argmax / top-k over the C tuple scores (Sec. 6.1,
+// Sec. 5.1.1), for FP32, BF16 and FP8 (OCP E4M3) operands with FP32 accumulation.
+//
+// Orientation: every layer computes out^T = W * in^T with output neurons as MFMA rows
+// (the A operand, weights) and packets as MFMA columns (the B operand, activations).
+// A 16x16 MFMA result leaves lane (g = lane/16, c = lane%16) holding rows 4g..4g+3 of
+// column c. The next layer's B operand wants, per lane, a few K values of column c; by
+// permuting the next layer's weight columns (its K order) once on the host, the rows a
+// lane already holds become exactly the K values it must supply, so activations never
+// leave registers between layers. Only the A/B symmetry of the MFMA K layout and the
+// output layout are relied on, not the hardware's internal K order.
+//
+// Layer-1 inputs are the header bits (MSB first over SIP, DIP, SP, DP, PROTO), made in
+// registers from the 16-byte header: 0/1 are exact in all three formats.
+// Weight fragments live in LDS when they fit (160 KB per CU) and are read from global
+// (L2-resident) otherwise; biases and the per-layer FP8 scales stay FP32.
+#include <algorithm>
+#include <cmath>
+
+#include "tang_internal.hpp"
+
+namespace tang {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <int PREC> struct FragT;
+template <> struct FragT<TANG_FP32> { using T = float; static constexpr int KB = 4; };
+template <> struct FragT<TANG_BF16> { using T = u32x4; static constexpr int KB = 32; };
+template <> struct FragT<TANG_FP8> { using T = u32x2; static constexpr int KB = 32; };
+
+struct MlpArgs {
+    int n_out;
+    int topk;
+    float deq[3];
+    float inv_a[3];
+};
+
+namespace {
+
+__device__ __forceinline__ f4 mma(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mma(u32x4 a, u32x4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mma(u32x2 a, u32x2 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a),
+                                                      __builtin_bit_cast(long, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((fl2){a, b}, bf16x2));
+}
+// Four non-negative floats (already clamped to <= 448) -> four E4M3 bytes, RNE.
+__device__ __forceinline__ uint32_t pack_fp8(float a, float b, float c, float d) {
+    uint32_t v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);
+}
+
+// Header words in MSB-first byte order: SIP, DIP, SP:DP, PROTO:0:0:0.
+__device__ __forceinline__ uint32_t hword(const uint4& h, int w) {
+    return w == 0 ? h.x : w == 1 ? h.y : w == 2 ? ((h.z << 16) | (h.z >> 16)) : ((h.w & 0xFFu) << 24);
+}
+
+// B fragment of the input bits for K block kb and lane group g.
+template <int PREC> struct Bits;
+template <> struct Bits<TANG_FP32> {
+    // feature f = 4kb + g: byte kb/2, bit (from the MSB) 4(kb&1) + g
+    __device__ static __forceinline__ float get(const uint4& h, int kb, int g) {
+        const int byte = kb >> 1;
+        const uint32_t w = hword(h, byte >> 2);
+        const int pos = 8 * (byte & 3) + 4 * (kb & 1) + g;
+        return (float)((w >> (31 - pos)) & 1u);
+    }
+};
+template <> struct Bits<TANG_BF16> {
+    // features 32kb + 8g + j (j = 0..7): byte 4kb + g, bit (from the MSB) j
+    __device__ static __forceinline__ u32x4 get(const uint4& h, int kb, int g) {
+        const uint32_t byte = (hword(h, kb) >> (24 - 8 * g)) & 0xFFu;
+        u32x4 r;
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            r[w] = ((byte >> (7 - 2 * w)) & 1u) * 0x3F80u | ((byte >> (6 - 2 * w)) & 1u) * 0x3F800000u;
+        return r;
+    }
+};
+template <> struct Bits<TANG_FP8> {
+    __device__ static __forceinline__ u32x2 get(const uint4& h, int kb, int g) {
+        const uint32_t byte = (hword(h, kb) >> (24 - 8 * g)) & 0xFFu;
+        u32x2 r;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v |= ((byte >> (7 - (4 * w + q))) & 1u) * (0x38u << (8 * q));
+            r[w] = v;
+        }
+        return r;
+    }
+};
+
+// One lane's A fragment `frag` of a layer: from LDS, or from global memory through a
+// buffer descriptor (lane offset in one VGPR, fragment offset as a scalar; reads past the
+// layer's size return zero instead of faulting).
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, float*) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+}
+__device__ __forceinline__ u32x2 bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, u32x2*) {
+    return __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0);
+}
+__device__ __forceinline__ u32x4 bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, u32x4*) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0);
+}
+
+template <bool IN_LDS, typename F>
+__device__ __forceinline__ F ldf(const F* lds, __amdgpu_buffer_rsrc_t r, uint32_t frag, uint32_t lane,
+                                 uint32_t sbase) {
+    if constexpr (IN_LDS) return lds[frag * 64 + lane];
+    else return bload(r, lane * (uint32_t)sizeof(F) + sbase, frag * 64u * (uint32_t)sizeof(F), (F*)nullptr);
+}
+
+// Bias + ReLU of one 16-row output tile and conversion into the next layer's B operand.
+template <int PREC, int NT, int KBN>
+__device__ __forceinline__ void epi_hidden(const f4 (&acc)[NT], int mt, const float* sbias, float deq,
+                                           float inv_next, int g,
+                                           typename FragT<PREC>::T (&dst)[KBN][NT]) {
+    float bv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bv[r] = sbias[16 * mt + 4 * g + r];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if constexpr (PREC == TANG_FP8) v[r] = fmaxf(acc[nt][r] * deq + bv[r], 0.0f);
+            else v[r] = fmaxf(acc[nt][r] + bv[r], 0.0f);
+        }
+        if constexpr (PREC == TANG_FP32) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[4 * mt + r][nt] = v[r];
+        } else if constexpr (PREC == TANG_BF16) {
+            dst[mt >> 1][nt][2 * (mt & 1)] = pack_bf16(v[0], v[1]);
+            dst[mt >> 1][nt][2 * (mt & 1) + 1] = pack_bf16(v[2], v[3]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = fminf(v[r] * inv_next, 448.0f);
+            dst[mt >> 1][nt][mt & 1] = pack_fp8(v[0], v[1], v[2], v[3]);
+        }
+    }
+}
+
+constexpr int kWaves = 8;
+
+template <int PREC, int H, int NT, int LDSM>
+__global__ __launch_bounds__(64 * kWaves) void k_mlp(
+    const uint4* __restrict__ hdr, uint32_t n, const typename FragT<PREC>::T* __restrict__ w1,
+    const typename FragT<PREC>::T* __restrict__ w2, const typename FragT<PREC>::T* __restrict__ w3,
+    const float* __restrict__ bias_g, MlpArgs a, uint32_t* __restrict__ cand,
+    float* __restrict__ logits, uint8_t* __restrict__ cand8) {
+    using F = typename FragT<PREC>::T;
+    constexpr int KB = FragT<PREC>::KB;
+    constexpr int KBN1 = kInPad / KB, KBNH = H / KB, MTH = H / 16;
+    // FP32 input blocks past feature 104 are all-zero on both operands: skipped
+    constexpr int KBN1_USED = PREC == TANG_FP32 ? 104 / KB : KBN1;
+    constexpr uint32_t n1 = MTH * KBN1 * 64, n2 = MTH * KBNH * 64, n3 = 2 * KBNH * 64;
+    constexpr uint32_t nb = 2 * H + kOutPad;
+
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    F* s1 = reinterpret_cast<F*>(smem);
+    F* s2 = s1 + ((LDSM & 1) ? n1 : 0);
+    F* s3 = s2 + ((LDSM & 2) ? n2 : 0);
+    float* sb = reinterpret_cast<float*>(s3 + ((LDSM & 4) ? n3 : 0));
+
+    {   // stage resident weights and the biases
+        auto copy16 = [&](void* dst, const void* src, uint32_t bytes) {
+            uint4* d = reinterpret_cast<uint4*>(dst);
+            const uint4* s = reinterpret_cast<const uint4*>(src);
+            for (uint32_t k = threadIdx.x; k < bytes / 16; k += blockDim.x) d[k] = s[k];
+        };
+        if (LDSM & 1) copy16(s1, w1, n1 * sizeof(F));
+        if (LDSM & 2) copy16(s2, w2, n2 * sizeof(F));
+        if (LDSM & 4) copy16(s3, w3, n3 * sizeof(F));
+        copy16(sb, bias_g, nb * sizeof(float));
+    }
+    __syncthreads();
+
+    const __amdgpu_buffer_rsrc_t r1 = __builtin_amdgcn_make_buffer_rsrc((void*)w1, 0, n1 * sizeof(F), 0x00020000);
+    const __amdgpu_buffer_rsrc_t r2 = __builtin_amdgcn_make_buffer_rsrc((void*)w2, 0, n2 * sizeof(F), 0x00020000);
+    const __amdgpu_buffer_rsrc_t r3 = __builtin_amdgcn_make_buffer_rsrc((void*)w3, 0, n3 * sizeof(F), 0x00020000);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+    const uint32_t tiles = (n + 16 * NT - 1) / (16 * NT);
+    const int C = a.n_out;
+    for (uint32_t tile = blockIdx.x * kWaves + wave; tile < tiles; tile += gridDim.x * kWaves) {
+        const uint32_t pbase = tile * 16u * NT;
+        // the weight loads are loop-invariant; hide that from LICM, which would otherwise
+        // hoist every fragment of the global-resident layers out of the tile loop
+        uint32_t sbase = 0;
+        asm volatile("" : "+s"(sbase));
+        uint4 hv[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const uint32_t p = pbase + nt * 16 + col;
+            hv[nt] = p < n ? hdr[p] : make_uint4(0, 0, 0, 0);
+        }
+        // layer 1: bits -> H
+        F a0[KBNH][NT];
+#pragma unroll
+        for (int mt = 0; mt < MTH; ++mt) {
+            f4 acc[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = (f4){0, 0, 0, 0};
+#pragma unroll
+            for (int kb = 0; kb < KBN1_USED; ++kb) {
+                const F A = ldf<(LDSM & 1) != 0>(s1, r1, mt * KBN1 + kb, lane, sbase);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[nt] = mma(A, Bits<PREC>::get(hv[nt], kb, g), acc[nt]);
+            }
+            epi_hidden<PREC, NT, KBNH>(acc, mt, sb, a.deq[0], a.inv_a[1], g, a0);
+            // keep the scheduler from hoisting every tile's fragment loads (register blow-up)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // layer 2: H -> H
+        F a1[KBNH][NT];
+#pragma unroll
+        for (int mt = 0; mt < MTH; ++mt) {
+            f4 acc[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = (f4){0, 0, 0, 0};
+#pragma unroll
+            for (int kb = 0; kb < KBNH; ++kb) {
+                const F A = ldf<(LDSM & 2) != 0>(s2, r2, mt * KBNH + kb, lane, sbase);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[nt] = mma(A, a0[kb][nt], acc[nt]);
+            }
+            epi_hidden<PREC, NT, KBNH>(acc, mt, sb + H, a.deq[1], a.inv_a[2], g, a1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // layer 3: H -> C (two 16-row tiles)
+        f4 z[2][NT];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) z[mt][nt] = (f4){0, 0, 0, 0};
+#pragma unroll
+            for (int kb = 0; kb < KBNH; ++kb) {
+                const F A = ldf<(LDSM & 4) != 0>(s3, r3, mt * KBNH + kb, lane, sbase);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) z[mt][nt] = mma(A, a1[kb][nt], z[mt][nt]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // scores, then top-k with ties to the lower tuple index
+        const float* sb3 = sb + 2 * H;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const uint32_t pkt = pbase + nt * 16 + col;
+            float v[8];
+            int cl[8];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = 16 * mt + 4 * g + r;
+                    float val = (PREC == TANG_FP8 ? z[mt][nt][r] * a.deq[2] : z[mt][nt][r]) + sb3[c];
+                    if (logits && pkt < n && c < C) logits[(size_t)pkt * C + c] = val;
+                    v[4 * mt + r] = (c < C && val == val) ? val : -INFINITY;
+                    cl[4 * mt + r] = c;
+                }
+            }
+            uint32_t packed = 0;
+            for (int k = 0; k < a.topk; ++k) {
+                float bv = v[0];
+                int bc = cl[0];
+#pragma unroll
+                for (int q = 1; q < 8; ++q)
+                    if (v[q] > bv) { bv = v[q]; bc = cl[q]; }   // classes ascend within a lane
+#pragma unroll
+                for (int o = 16; o <= 32; o <<= 1) {
+                    const float ov = __shfl_xor(bv, o, 64);
+                    const int oc = __shfl_xor(bc, o, 64);
+                    if (ov > bv || (ov == bv && oc < bc)) { bv = ov; bc = oc; }
+                }
+                packed |= (uint32_t)bc << (8 * k);
+                if (cand8 && g == 0 && pkt < n) cand8[(size_t)pkt * a.topk + k] = (uint8_t)bc;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (cl[q] == bc) v[q] = -INFINITY;
+                // a removed class must never win again: push it below -inf ties
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (cl[q] == bc) cl[q] = 1 << 20;
+            }
+            if (cand && g == 0 && pkt < n) cand[pkt] = packed;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Host side: quantisers, fragment swizzle, upload, launch.
+
+uint16_t f32_to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return 0x7FC0;
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// OCP FP8 E4M3: bias 7, 3 fraction bits, no infinity, max 448; RNE, saturating.
+uint8_t f32_to_e4m3(float f) {
+    const uint8_t sign = std::signbit(f) ? 0x80 : 0x00;
+    double x = std::fabs((double)f);
+    if (x != x) return 0x7F;
+    if (x >= 448.0) return sign | 0x7E;
+    if (x < std::ldexp(1.0, -6)) return sign | (uint8_t)std::nearbyint(x * 512.0);
+    int e;
+    const double m = std::frexp(x, &e);  // x = m 2^e, m in [0.5, 1)
+    int E = e - 1;
+    double f8 = std::nearbyint((2.0 * m - 1.0) * 8.0);
+    if (f8 == 8.0) { ++E; f8 = 0.0; }
+    int code = ((E + 7) << 3) | (int)f8;
+    if (code > 0x7E) code = 0x7E;
+    return sign | (uint8_t)code;
+}
+
+// Input column (of W[out][in]) that lane group g, element j of K block kb carries.
+int in_col(int prec, int layer, int kb, int g, int j) {
+    if (prec == TANG_FP32) return layer == 0 ? 4 * kb + g : 16 * (kb / 4) + 4 * g + (kb % 4);
+    return layer == 0 ? 32 * kb + 8 * g + j : 16 * (2 * kb + (j >> 2)) + 4 * g + (j & 3);
+}
+
+}  // namespace
+
+void model_free(ModelDev& m) {
+    for (auto& p : m.w) {
+        if (p) hipFree(p);
+        p = nullptr;
+    }
+    if (m.bias) hipFree(m.bias);
+    m.bias = nullptr;
+    m.loaded = 0;
+    m.bytes = 0;
+}
+
+int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* const* W,
+                  const float* const* b, tang_precision_t p, const float* act_scales) {
+    if (!d || !W || !b) return fail(TANG_EINVAL, "NULL model argument");
+    const int C = (int)rs->sigs.size();
+    if (d->n_layers != 3) return fail(TANG_EINVAL, "only 3-layer MLPs (104 -> H -> H -> C) are supported");
+    if (d->dims[0] != 104) return fail(TANG_EINVAL, "input width must be 104 header bits");
+    const int H = (int)d->dims[1];
+    if ((int)d->dims[2] != H || (H != 128 && H != 256))
+        return fail(TANG_EINVAL, "hidden widths must be equal and 128 or 256");
+    if ((int)d->dims[3] != C || C < 1 || C > kOutPad)
+        return fail(TANG_EINVAL, "output width must equal the number of tuples (1..32)");
+    if (d->topk < 1 || d->topk > TANG_MAX_TOPK || (int)d->topk > C)
+        return fail(TANG_EINVAL, "topk must be in 1..min(4, C)");
+    if (p != TANG_FP32 && p != TANG_BF16 && p != TANG_FP8) return fail(TANG_EINVAL, "bad precision");
+    if (p == TANG_FP8) {
+        if (!act_scales) return fail(TANG_EINVAL, "FP8 needs act_scales");
+        for (int l = 1; l < 3; ++l)
+            if (!(act_scales[l] > 0.0f) || !std::isfinite(act_scales[l]))
+                return fail(TANG_EINVAL, "act_scales must be positive and finite");
+    } else if (act_scales) {
+        return fail(TANG_EINVAL, "act_scales only apply to FP8");
+    }
+    for (int l = 0; l < 3; ++l)
+        if (!W[l] || !b[l]) return fail(TANG_EINVAL, "NULL weight or bias");
+
+    ModelDev m;
+    m.prec = p;
+    m.hidden = H;
+    m.n_out = C;
+    m.topk = (int)d->topk;
+    const int KB = p == TANG_FP32 ? 4 : 32, E = p == TANG_FP32 ? 1 : 8;
+    const int esz = p == TANG_FP32 ? 4 : p == TANG_BF16 ? 2 : 1;
+    const int outs[3] = {H, H, C}, ins[3] = {104, H, H};
+    const int outp[3] = {H, H, kOutPad}, inp[3] = {kInPad, H, H};
+    for (int l = 0; l < 3; ++l) {
+        float s_w = 1.0f, inv_w = 1.0f, s_a = 1.0f;
+        if (p == TANG_FP8) {
+            float amax = 0.0f;
+            for (size_t k = 0; k < (size_t)outs[l] * ins[l]; ++k) amax = std::max(amax, std::fabs(W[l][k]));
+            s_w = amax > 0.0f ? amax / 448.0f : 1.0f;
+            inv_w = 1.0f / s_w;
+            s_a = l == 0 ? 1.0f : act_scales[l];
+            m.deq[l] = s_a * s_w;
+            m.inv_a[l] = 1.0f / s_a;
+        }
+        const int MT = outp[l] / 16, KBN = inp[l] / KB;
+        std::vector<unsigned char> buf((size_t)MT * KBN * 64 * E * esz, 0);
+        for (int mt = 0; mt < MT; ++mt)
+            for (int kb = 0; kb < KBN; ++kb)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int j = 0; j < E; ++j) {
+                        const int row = 16 * mt + (lane & 15), g = lane >> 4;
+                        const int c = in_col(p, l, kb, g, j);
+                        const float w = (row < outs[l] && c < ins[l]) ? W[l][(size_t)row * ins[l] + c] : 0.0f;
+                        const size_t at = ((((size_t)mt * KBN + kb) * 64 + lane) * E + j) * esz;
+                        if (p == TANG_FP32) std::memcpy(&buf[at], &w, 4);
+                        else if (p == TANG_BF16) {
+                            const uint16_t q = f32_to_bf16(w);
+                            std::memcpy(&buf[at], &q, 2);
+                        } else {
+                            buf[at] = f32_to_e4m3(w * inv_w);
+                        }
+                    }
+        hipError_t e = hipMalloc(&m.w[l], buf.size());
+        if (e == hipSuccess) e = hipMemcpy(m.w[l], buf.data(), buf.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { model_free(m); return hip_fail(e, "model upload"); }
+        m.wbytes[l] = buf.size();
+        m.bytes += buf.size();
+    }
+    std::vector<float> bias(2 * H + kOutPad, 0.0f);
+    for (int k = 0; k < H; ++k) { bias[k] = b[0][k]; bias[H + k] = b[1][k]; }
+    for (int k = 0; k < C; ++k) bias[2 * H + k] = b[2][k];
+    hipError_t e = hipMalloc(&m.bias, bias.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(m.bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { model_free(m); return hip_fail(e, "bias upload"); }
+    m.bytes += bias.size() * 4;
+    m.loaded = 1;
+    model_free(rs->model);
+    rs->model = m;
+    rs->version++;
+    return TANG_OK;
+}
+
+namespace {
+
+template <int PREC, int H, int NT, int LDSM>
+hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, uint32_t* cand,
+                    float* logits, uint8_t* cand8, hipStream_t s) {
+    using F = typename FragT<PREC>::T;
+    constexpr int KB = FragT<PREC>::KB;
+    constexpr size_t n1 = (H / 16) * (kInPad / KB) * 64, n2 = (H / 16) * (H / KB) * 64,
+                     n3 = 2 * (H / KB) * 64;
+    const size_t lds = ((LDSM & 1) ? n1 : 0) * sizeof(F) + ((LDSM & 2) ? n2 : 0) * sizeof(F) +
+                       ((LDSM & 4) ? n3 : 0) * sizeof(F) + (2 * H + kOutPad) * sizeof(float);
+    auto kern = k_mlp<PREC, H, NT, LDSM>;
+    static int attr_done = 0;  // per instantiation
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+        attr_done = 1;
+    }
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64 * kWaves, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    const uint32_t tiles = (n + 16 * NT - 1) / (16 * NT);
+    const uint32_t want = (tiles + kWaves - 1) / kWaves;
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(want, (uint32_t)(cus * per_cu)));
+    MlpArgs a;
+    a.n_out = m.n_out;
+    a.topk = m.topk;
+    for (int l = 0; l < 3; ++l) { a.deq[l] = m.deq[l]; a.inv_a[l] = m.inv_a[l]; }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kWaves), lds, s,
+                       reinterpret_cast<const uint4*>(d_hdr), n, (const F*)m.w[0], (const F*)m.w[1],
+                       (const F*)m.w[2], m.bias, a, cand, logits, cand8);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
+                      uint32_t* d_cand_packed, float* d_logits, uint8_t* d_cand8, hipStream_t s) {
+    const ModelDev& m = rs->model;
+    const size_t chunk = (size_t)1 << 30;
+    for (size_t base = 0; base < n; base += chunk) {
+        const uint32_t k = (uint32_t)std::min(chunk, n - base);
+        const tang_header_t* h = d_hdr + base;
+        uint32_t* c = d_cand_packed ? d_cand_packed + base : nullptr;
+        float* lg = d_logits ? d_logits + base * (size_t)m.n_out : nullptr;
+        uint8_t* c8 = d_cand8 ? d_cand8 + base * (size_t)m.topk : nullptr;
+        hipError_t e;
+        // LDSM: which layers' fragments sit in LDS (bit l = layer l) -- 160 KB per CU
+        if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 7>(m, h, k, c, lg, c8, s);
+        else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0>(m, h, k, c, lg, c8, s);
+        else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 7>(m, h, k, c, lg, c8, s);
+        else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 6>(m, h, k, c, lg, c8, s);
+        else if (m.hidden == 128) e = launch_t<TANG_FP8, 128, 2, 7>(m, h, k, c, lg, c8, s);
+        else e = launch_t<TANG_FP8, 256, 2, 7>(m, h, k, c, lg, c8, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace tang

@@ -1,0 +1,395 @@
+// Serving loop: continuous batching of classify requests over device-resident rulesets.
+//
+// One persistent host thread owns S stream slots. Each slot has pinned host staging
+// and device buffers for one batch. While a slot is free and requests are pending, the
+// loop takes the oldest pending request, packs further pending requests of the same
+// ruleset behind it (arrival order, up to the batch limit), admits them if the packets
+// and staging bytes in flight stay within the configured limits, copies their headers
+// in, replays the HIP graph captured for (ruleset, batch size class, slot), copies the
+// results out and records an event. Completed slots hand results to their requests.
+// Requests that arrive while others are on the GPU are admitted as slots and budget
+// free up, so batches of different requests and rulesets overlap on the device.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
+
+#include "tang_internal.hpp"
+
+namespace {
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct ReqState {
+    uint32_t tag = 0;
+    const tang_header_t* hdr = nullptr;
+    size_t n = 0;
+    uint32_t* out = nullptr;
+    uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+    int status = TANG_OK;
+    bool done = false;
+    std::mutex mu;
+    std::condition_variable cv;
+};
+
+struct StreamSlot {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    tang_header_t* h_hdr = nullptr;  // pinned
+    uint32_t* h_out = nullptr;       // pinned
+    tang_header_t* d_hdr = nullptr;
+    uint32_t* d_out = nullptr;
+    bool busy = false;
+    size_t total = 0;
+    std::vector<std::shared_ptr<ReqState>> reqs;
+    std::vector<size_t> offs;
+};
+
+struct GraphEntry {
+    uint64_t version = ~0ull;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct tang_req_s {
+    std::shared_ptr<ReqState> st;
+};
+
+struct tang_server_s {
+    int device = 0;
+    tang_server_cfg_t cfg{};
+    std::vector<tang_ruleset_t*> rulesets;
+    std::vector<StreamSlot> slots;
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, GraphEntry> graphs;  // (tag, class, slot)
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::shared_ptr<ReqState>> pending;
+    size_t inflight_pkts = 0, inflight_bytes = 0;
+    bool stop = false;
+    std::thread th;
+    std::vector<char> warmed;
+
+    void loop();
+    void finish(StreamSlot& s, int status);
+    int launch(uint32_t slot_idx, uint32_t tag, std::vector<std::shared_ptr<ReqState>>& batch,
+               size_t total);
+    int graph_for(uint32_t tag, uint32_t cls, uint32_t slot_idx, hipGraphExec_t* out);
+};
+
+using namespace tang;
+
+static constexpr size_t kPktBytes = sizeof(tang_header_t) + sizeof(uint32_t);
+
+int tang_server_s::graph_for(uint32_t tag, uint32_t cls, uint32_t si, hipGraphExec_t* out) {
+    tang_ruleset_t* rs = rulesets[tag];
+    GraphEntry& g = graphs[std::make_tuple(tag, cls, si)];
+    if (g.exec && g.version == rs->version) {
+        *out = g.exec;
+        return TANG_OK;
+    }
+    if (g.exec) {
+        hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+    }
+    StreamSlot& s = slots[si];
+    TANG_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeRelaxed));
+    int rc = tang_classify(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s.stream, &graph);
+    if (rc) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        g.exec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    g.version = rs->version;
+    *out = g.exec;
+    return TANG_OK;
+}
+
+int tang_server_s::launch(uint32_t si, uint32_t tag, std::vector<std::shared_ptr<ReqState>>& batch,
+                          size_t total) {
+    StreamSlot& s = slots[si];
+    tang_ruleset_t* rs = rulesets[tag];
+    s.reqs = batch;
+    s.offs.clear();
+    s.total = total;
+    size_t off = 0;
+    for (auto& r : batch) {
+        s.offs.push_back(off);
+        std::memcpy(s.h_hdr + off, r->hdr, r->n * sizeof(tang_header_t));
+        off += r->n;
+    }
+    size_t cls = 32;
+    while (cls < total) cls <<= 1;
+    TANG_HIP(hipMemcpyAsync(s.d_hdr, s.h_hdr, total * sizeof(tang_header_t), hipMemcpyHostToDevice,
+                            s.stream));
+    if (!warmed[tag]) {  // first use: eager call sets up kernel attributes before any capture
+        int rc = tang_classify(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr);
+        if (rc) return rc;
+        TANG_HIP(hipStreamSynchronize(s.stream));
+        warmed[tag] = 1;
+    }
+    if (cfg.use_graphs) {
+        hipGraphExec_t exec = nullptr;
+        int rc = graph_for(tag, (uint32_t)cls, si, &exec);
+        if (rc) return rc;
+        TANG_HIP(hipGraphLaunch(exec, s.stream));
+    } else {
+        int rc = tang_classify(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr);
+        if (rc) return rc;
+    }
+    TANG_HIP(hipMemcpyAsync(s.h_out, s.d_out, total * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                            s.stream));
+    TANG_HIP(hipEventRecord(s.ev, s.stream));
+    s.busy = true;
+    return TANG_OK;
+}
+
+void tang_server_s::finish(StreamSlot& s, int status) {
+    const uint64_t t = now_ns();
+    for (size_t k = 0; k < s.reqs.size(); ++k) {
+        auto& r = s.reqs[k];
+        if (status == TANG_OK) std::memcpy(r->out, s.h_out + s.offs[k], r->n * sizeof(uint32_t));
+        {
+            std::lock_guard<std::mutex> g(r->mu);
+            r->t_done = t;
+            r->status = status;
+            r->done = true;
+        }
+        r->cv.notify_all();
+    }
+    {
+        std::lock_guard<std::mutex> g(mu);
+        inflight_pkts -= s.total;
+        inflight_bytes -= s.total * kPktBytes;
+    }
+    s.reqs.clear();
+    s.busy = false;
+    s.total = 0;
+}
+
+void tang_server_s::loop() {
+    hipSetDevice(device);
+    for (;;) {
+        bool progressed = false;
+        for (auto& s : slots) {
+            if (!s.busy) continue;
+            hipError_t q = hipEventQuery(s.ev);
+            if (q == hipSuccess) {
+                finish(s, TANG_OK);
+                progressed = true;
+            } else if (q != hipErrorNotReady) {
+                finish(s, TANG_EDEVICE);
+                progressed = true;
+            }
+        }
+        std::unique_lock<std::mutex> lk(mu);
+        bool any_busy = false;
+        for (auto& s : slots) any_busy |= s.busy;
+        if (stop && pending.empty() && !any_busy) break;
+        for (uint32_t si = 0; si < slots.size() && !pending.empty(); ++si) {
+            if (slots[si].busy) continue;
+            // oldest request decides the ruleset; same-ruleset requests behind it join
+            const uint32_t tag = pending.front()->tag;
+            std::vector<std::shared_ptr<ReqState>> batch;
+            size_t total = 0;
+            for (auto it = pending.begin(); it != pending.end();) {
+                if ((*it)->tag != tag) { ++it; continue; }
+                const size_t n = (*it)->n;
+                if (total + n > cfg.max_batch) break;
+                if (inflight_pkts + total + n > cfg.max_inflight_packets) break;
+                if (inflight_bytes + (total + n) * kPktBytes > cfg.mem_budget_bytes) break;
+                batch.push_back(*it);
+                total += n;
+                it = pending.erase(it);
+            }
+            if (batch.empty()) break;  // not admissible yet: wait for completions
+            inflight_pkts += total;
+            inflight_bytes += total * kPktBytes;
+            const uint64_t t = now_ns();
+            for (auto& r : batch) r->t_admit = t;
+            lk.unlock();
+            int rc = launch(si, tag, batch, total);
+            if (rc != TANG_OK) {
+                StreamSlot& s = slots[si];
+                s.reqs = batch;
+                s.total = total;
+                s.offs.assign(batch.size(), 0);
+                finish(s, rc);
+            }
+            progressed = true;
+            lk.lock();
+        }
+        if (!progressed) {
+            any_busy = false;
+            for (auto& s : slots) any_busy |= s.busy;
+            if (any_busy) cv.wait_for(lk, std::chrono::microseconds(20));
+            else if (pending.empty() && !stop) cv.wait_for(lk, std::chrono::milliseconds(50));
+        }
+    }
+}
+
+static void free_server(tang_server_t* srv) {
+    hipSetDevice(srv->device);
+    for (auto& kv : srv->graphs)
+        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+    for (auto& s : srv->slots) {
+        if (s.stream) hipStreamSynchronize(s.stream);
+        if (s.ev) hipEventDestroy(s.ev);
+        if (s.stream) hipStreamDestroy(s.stream);
+        if (s.h_hdr) hipHostFree(s.h_hdr);
+        if (s.h_out) hipHostFree(s.h_out);
+        if (s.d_hdr) hipFree(s.d_hdr);
+        if (s.d_out) hipFree(s.d_out);
+    }
+    delete srv;
+}
+
+extern "C" {
+
+int tang_server_create(int device, const tang_server_cfg_t* cfg, tang_server_t** out) {
+    try {
+        if (!out) return fail(TANG_EINVAL, "out is NULL");
+        *out = nullptr;
+        int count = 0;
+        hipError_t ec = hipGetDeviceCount(&count);
+        if (ec != hipSuccess) return hip_fail(ec, "hipGetDeviceCount");
+        if (count == 0) return fail(TANG_EDEVICE, "no HIP device available");
+        if (device < 0 || device >= count) return fail(TANG_EINVAL, "bad device ordinal");
+        tang_server_cfg_t c{};
+        if (cfg) c = *cfg;
+        if (c.n_streams == 0) c.n_streams = 4;
+        if (c.max_batch == 0) c.max_batch = 65536;
+        if (c.n_streams > 8) return fail(TANG_EINVAL, "n_streams must be 1..8");
+        if (c.max_batch < 32 || (c.max_batch & (c.max_batch - 1)))
+            return fail(TANG_EINVAL, "max_batch must be a power of two >= 32");
+        if (c.max_inflight_packets == 0) c.max_inflight_packets = c.n_streams * c.max_batch;
+        if (c.mem_budget_bytes == 0) c.mem_budget_bytes = (size_t)c.n_streams * c.max_batch * kPktBytes;
+        auto* srv = new tang_server_t();
+        srv->device = device;
+        srv->cfg = c;
+        srv->slots.resize(c.n_streams);
+        hipError_t e = hipSetDevice(device);
+        for (auto& s : srv->slots) {
+            if (e == hipSuccess) e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_hdr, c.max_batch * sizeof(tang_header_t), 0);
+            if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_out, c.max_batch * sizeof(uint32_t), 0);
+            if (e == hipSuccess) e = hipMalloc(&s.d_hdr, c.max_batch * sizeof(tang_header_t));
+            if (e == hipSuccess) e = hipMalloc(&s.d_out, c.max_batch * sizeof(uint32_t));
+            if (e == hipSuccess) e = hipMemset(s.d_hdr, 0, c.max_batch * sizeof(tang_header_t));
+        }
+        if (e != hipSuccess) {
+            free_server(srv);
+            return hip_fail(e, "tang_server_create");
+        }
+        srv->th = std::thread([srv] { srv->loop(); });
+        *out = srv;
+        return TANG_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(TANG_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(TANG_EINVAL, "internal error");
+    }
+}
+
+int tang_server_add_ruleset(tang_server_t* srv, tang_ruleset_t* rs, uint32_t* tag) {
+    if (!srv || !rs || !tag) return fail(TANG_EINVAL, "NULL argument");
+    if (rs->device != srv->device) return fail(TANG_EINVAL, "ruleset lives on another device");
+    std::lock_guard<std::mutex> g(srv->mu);
+    *tag = (uint32_t)srv->rulesets.size();
+    srv->rulesets.push_back(rs);
+    srv->warmed.push_back(0);
+    return TANG_OK;
+}
+
+int tang_server_submit(tang_server_t* srv, uint32_t tag, const tang_header_t* hdr, size_t n,
+                       uint32_t* out, tang_req_t** req) {
+    try {
+        if (!srv || !req) return fail(TANG_EINVAL, "NULL argument");
+        *req = nullptr;
+        if (n && (!hdr || !out)) return fail(TANG_EINVAL, "NULL buffer");
+        auto st = std::make_shared<ReqState>();
+        st->tag = tag;
+        st->hdr = hdr;
+        st->n = n;
+        st->out = out;
+        st->t_submit = now_ns();
+        {
+            std::lock_guard<std::mutex> g(srv->mu);
+            if (tag >= srv->rulesets.size()) return fail(TANG_EINVAL, "unknown ruleset tag");
+            if (n > srv->cfg.max_batch || n > srv->cfg.max_inflight_packets ||
+                n * kPktBytes > srv->cfg.mem_budget_bytes)
+                return fail(TANG_EBUSY, "request larger than the server's limits");
+            if (srv->stop) return fail(TANG_EBUSY, "server is stopping");
+            if (n == 0) {
+                st->t_admit = st->t_done = st->t_submit;
+                st->done = true;
+            } else {
+                srv->pending.push_back(st);
+            }
+        }
+        srv->cv.notify_all();
+        *req = new tang_req_t{st};
+        return TANG_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(TANG_ENOMEM, "host allocation failed");
+    }
+}
+
+int tang_server_wait(tang_req_t* req, int64_t timeout_us) {
+    if (!req) return fail(TANG_EINVAL, "NULL request");
+    auto& st = *req->st;
+    std::unique_lock<std::mutex> lk(st.mu);
+    if (timeout_us < 0) {
+        st.cv.wait(lk, [&] { return st.done; });
+    } else if (!st.cv.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return st.done; })) {
+        return fail(TANG_ETIMEOUT, "request not done yet");
+    }
+    if (st.status != TANG_OK) return fail(st.status, "request failed on the device");
+    return TANG_OK;
+}
+
+int tang_server_poll(const tang_req_t* req) {
+    if (!req) return 0;
+    std::lock_guard<std::mutex> g(req->st->mu);
+    return req->st->done ? 1 : 0;
+}
+
+int tang_server_req_times(const tang_req_t* req, uint64_t* submit_ns, uint64_t* admit_ns,
+                          uint64_t* done_ns) {
+    if (!req) return fail(TANG_EINVAL, "NULL request");
+    std::lock_guard<std::mutex> g(req->st->mu);
+    if (submit_ns) *submit_ns = req->st->t_submit;
+    if (admit_ns) *admit_ns = req->st->t_admit;
+    if (done_ns) *done_ns = req->st->t_done;
+    return TANG_OK;
+}
+
+void tang_server_req_free(tang_req_t* req) { delete req; }
+
+int tang_server_destroy(tang_server_t* srv) {
+    if (!srv) return fail(TANG_EINVAL, "NULL server");
+    {
+        std::lock_guard<std::mutex> g(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv.notify_all();
+    if (srv->th.joinable()) srv->th.join();
+    free_server(srv);
+    return TANG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,212 @@
+// Internal declarations of the gfx950 packet classifier: device data layout, the slot
+// hash, the ruleset object and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/tang.h"
+
+namespace tang {
+
+// ---------------------------------------------------------------------------------------
+// Device layout.
+//
+// Slot (16 B): one bucket of the global open-addressing table. The key is the full
+// (tuple, SIP & mask_t, DIP & mask_t), so an answer never depends on the hash function.
+//   tl = tuple << 24 | bucket length; kEmptyTL marks a never-used slot.
+//   off = first record of the bucket in the record array.
+struct alignas(16) Slot {
+    uint32_t ms, md, tl, off;
+};
+constexpr uint32_t kEmptyTL = 0xFFFFFFFFu;
+constexpr uint32_t kMaxBucketLen = 0x00FFFFFFu;
+
+// Rec (32 B): one rule as the bucket scan reads it. Two 16-byte loads.
+//   sip, dip : prefix values, bits beyond the length zeroed
+//   sp, dp   : lo | hi << 16 (inclusive)
+//   meta     : sip_len (bits 0-5) | dip_len (6-11) | proto (12-19) | exact-proto (20)
+//              | tuple (21-25)
+//   cmask    : conflict tuples -- tuples that hold a higher-priority rule whose box
+//              meets this rule's box (a superset after deletes)
+//   prio, id : the (priority, id) key; kDead marks a vacated record
+struct alignas(16) Rec {
+    uint32_t sip, dip, sp, dp, meta, cmask, prio, id;
+};
+constexpr uint32_t kDead = 0xFFFFFFFFu;
+
+__host__ __device__ inline uint32_t meta_pack(uint32_t sl, uint32_t dl, uint32_t proto,
+                                              uint32_t exact, uint32_t tuple) {
+    return sl | (dl << 6) | (proto << 12) | (exact << 20) | (tuple << 21);
+}
+__host__ __device__ inline uint32_t meta_sl(uint32_t m) { return m & 63u; }
+__host__ __device__ inline uint32_t meta_dl(uint32_t m) { return (m >> 6) & 63u; }
+__host__ __device__ inline uint32_t meta_proto(uint32_t m) { return (m >> 12) & 255u; }
+__host__ __device__ inline uint32_t meta_exact(uint32_t m) { return (m >> 20) & 1u; }
+__host__ __device__ inline uint32_t meta_tuple(uint32_t m) { return (m >> 21) & 31u; }
+
+// Prefix mask of length l (0..32): the top l bits; l = 0 gives 0 (no shift by 32).
+__host__ __device__ inline uint32_t pmask(uint32_t l) {
+    return l == 0 ? 0u : (0xFFFFFFFFu << (32u - l));
+}
+
+// Per-tuple data: masks and the smallest (priority, id) key of any rule ever placed in
+// the tuple (a lower bound after deletes, used to stop searching tuples early).
+struct TupleDev {
+    uint32_t smask, dmask, best_prio, best_id;
+};
+struct TupleTable {
+    TupleDev t[TANG_MAX_TUPLES];
+    uint8_t order[TANG_MAX_TUPLES];  // tuple indices by ascending best key
+    uint32_t n;                       // number of tuples
+    uint32_t all_mask;                // bits of all tuples
+    uint32_t slot_mask;               // slots - 1
+    uint32_t pad;
+};
+
+// Slot index: MurmurHash3's 64-bit finaliser (fmix64, Appleby, public domain) over the
+// packed masked addresses, salted by the tuple index (golden-ratio multiple).
+__host__ __device__ inline uint32_t slot_hash(uint32_t t, uint32_t ms, uint32_t md) {
+    uint64_t k = ((uint64_t)ms << 32) | md;
+    k ^= (uint64_t)(t + 1u) * 0x9E3779B97F4A7C15ull;
+    k ^= k >> 33;
+    k *= 0xFF51AFD7ED558CCDull;
+    k ^= k >> 33;
+    k *= 0xC4CEB9FE1A85EC53ull;
+    k ^= k >> 33;
+    return (uint32_t)k;
+}
+
+// Device-side counters for tang_stats_t.
+struct StatsDev {
+    unsigned long long packets, probes, slots, records, top1, fallbacks, nomatch;
+};
+
+// Rule box used by the conflict-mask kernels (key order), 32 B.
+struct alignas(16) BoxDev {
+    uint32_t slo, shi, dlo, dhi, sp, dp, pt, pos;  // pt = proto | exact << 8 | tuple << 16
+};
+
+// ---------------------------------------------------------------------------------------
+// Model on the device.
+
+constexpr int kMaxHidden = 256;
+constexpr int kOutPad = 32;   // output classes padded to 2 MFMA tiles
+constexpr int kInPad = 128;   // 104 input bits padded to 128
+
+struct ModelDev {
+    int loaded = 0;
+    tang_precision_t prec = TANG_FP32;
+    int hidden = 0;
+    int n_out = 0;    // C
+    int topk = 1;
+    // Weight fragments for the three layers in MFMA A-operand order, and biases.
+    void* w[3] = {nullptr, nullptr, nullptr};
+    size_t wbytes[3] = {0, 0, 0};
+    float* bias = nullptr;   // [hidden | hidden | 32] floats
+    float deq[3] = {1, 1, 1};     // FP8: s_a * s_w per layer
+    float inv_a[3] = {1, 1, 1};   // FP8: 1 / s_a per layer (layer 0 unused)
+    size_t bytes = 0;
+};
+
+}  // namespace tang
+
+// ---------------------------------------------------------------------------------------
+// The ruleset object behind tang_ruleset_t.
+
+struct tang_ruleset_s {
+    struct HRule {
+        tang_rule_t r;      // normalised
+        uint32_t tuple;
+        uint32_t bucket;
+        uint32_t pos;       // record index on the device
+        bool live;
+    };
+    struct Bucket {
+        uint32_t t, ms, md;
+        uint32_t slot;
+        uint32_t off, cap;
+        std::vector<uint32_t> members;  // rule handles in (priority, id) order
+    };
+    struct BKey {
+        uint32_t t, ms, md;
+        bool operator==(const BKey& o) const { return t == o.t && ms == o.ms && md == o.md; }
+    };
+    struct BKeyHash {
+        size_t operator()(const BKey& k) const {
+            return (size_t)tang::slot_hash(k.t, k.ms, k.md);
+        }
+    };
+
+    int device = TANG_HOST_ONLY;
+    std::vector<HRule> rules;                      // handle-indexed, never shrinks
+    std::unordered_map<uint32_t, uint32_t> id2h;   // live id -> handle
+    size_t n_live = 0;
+    std::vector<std::pair<uint8_t, uint8_t>> sigs; // tuple signatures
+    std::vector<uint64_t> tuple_best;              // lower bound on keys per tuple
+    std::vector<Bucket> buckets;
+    std::unordered_map<BKey, uint32_t, BKeyHash> bucket_of;
+    std::vector<tang::Slot> slots;                 // host mirror of the slot table
+    uint32_t rec_used = 0, rec_cap = 0;
+
+    // device state
+    tang::Slot* d_slots = nullptr;
+    tang::Rec* d_recs = nullptr;
+    tang::TupleTable* d_tt = nullptr;
+    tang::StatsDev* d_stats = nullptr;
+    hipStream_t upd_stream = nullptr;
+    tang::ModelDev model;
+    std::mutex stats_mu;
+    uint64_t version = 0;   // bumped by every change that captured launches depend on
+
+    size_t device_bytes() const;
+};
+
+namespace tang {
+
+// Error reporting (thread-local message + code).
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+#define TANG_HIP(call)                                         \
+    do {                                                       \
+        hipError_t _e = (call);                                \
+        if (_e != hipSuccess) return ::tang::hip_fail(_e, #call); \
+    } while (0)
+
+// Host tuple space (tss.cpp).
+int validate_rule(const tang_rule_t& r);
+tang_rule_t normalise(const tang_rule_t& r);
+inline uint64_t key_of(const tang_rule_t& r) { return ((uint64_t)r.priority << 32) | r.id; }
+int build_host(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n);
+int upload_all(tang_ruleset_t* rs);
+TupleTable make_tuple_table(const tang_ruleset_t* rs);
+Rec make_rec(const tang_ruleset_t* rs, uint32_t h);
+int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n);
+int apply_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n);
+
+// Kernel launchers (k_classify.hip, k_build.hip, k_mlp.hip).
+hipError_t launch_classify(const tang_ruleset_t* rs, const tang_header_t* d_hdr,
+                           uint32_t* d_out, size_t n, int kcand, hipStream_t s, bool stats);
+hipError_t launch_conflict_build(const BoxDev* d_boxes, size_t n, Rec* d_recs, uint32_t all_mask,
+                                 hipStream_t s);
+hipError_t launch_conflict_update(Rec* d_recs, uint32_t rec_used, const uint32_t* d_new_pos,
+                                  uint32_t n_new, hipStream_t s);
+hipError_t launch_move_records(Rec* d_recs, const Rec* d_src_recs, const uint32_t* d_src,
+                               const uint32_t* d_dst, uint32_t n, Rec* d_stage, hipStream_t s);
+hipError_t launch_scatter_slots(Slot* d_slots, const uint32_t* d_idx, const Slot* d_val,
+                                uint32_t n, hipStream_t s);
+hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
+                      uint32_t* d_cand_packed, float* d_logits, uint8_t* d_cand8,
+                      hipStream_t s);
+int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* const* W,
+                  const float* const* b, tang_precision_t p, const float* act_scales);
+void model_free(ModelDev& m);
+
+}  // namespace tang

@@ -1,0 +1,219 @@
+"""GPU parity: every rule id from the HIP path equals the linear-scan oracle's, bit for
+bit, on the worked example, on exhaustive tiny universes, and on the benchmark
+workloads (full answers at sizes the oracle finishes in seconds; sampled answers plus
+invariants that hold at any size at the 512k-rule, 16M-header size)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2601_03187_amd import synth, train
+from paper_2601_03187_amd import tang as T
+from tests import _golden
+from tests._gpu import classify_dev, keys_of, torch_cuda
+
+pytestmark = pytest.mark.gpu
+NO = T.TANG_NO_MATCH
+
+
+def _load(rs, Ws, bs, prec, topk=1, sc=None):
+    T.tang_model_load(rs, Ws, bs, prec, topk=topk, act_scales=sc if prec == "fp8" else None)
+
+
+def test_table1_grid_probe_all_and_with_models(golden_tab_rules):
+    torch_cuda()
+    g = golden_tab_rules
+    rng = np.random.default_rng(3)
+    pts, pk = _golden.grid_packets(rng, reps=4)
+    want = np.array([NO if g["grid"][p] is None else int(g["grid"][p][1:]) for p in pts], dtype=np.uint32)
+    rs = T.tang_ruleset_create(0, g["array"])
+    try:
+        assert np.array_equal(classify_dev(rs, pk), want)
+        names = [t[0] for t in g["tuples"]]
+        for rname, targets in g["conflict"].items():
+            want_m = sum(1 << names.index(t) for t in targets)
+            assert T.tang_ruleset_conflict_mask(rs, int(rname[1:])) == want_m, rname
+        # every constant prediction (each tuple forced as argmax), all precisions
+        for prec in ("fp32", "bf16", "fp8"):
+            for winner in range(5):
+                Ws, bs = train.constant_winner_weights(5, 128, winner)
+                _load(rs, Ws, bs, prec, sc=[1.0, 1.0, 1.0])
+                assert np.array_equal(classify_dev(rs, pk), want), (prec, winner)
+        T.tang_model_unload(rs)
+        # Sec. 4.3 / 5.2.1 insertions on the device
+        for (name, prio, x, y, _) in g["inserts"]:
+            T.tang_insert(rs, np.array([_golden.make_rule(name, prio, x, y)], dtype=synth.RULE_DTYPE))
+        grid = dict(g["grid"])
+        for (cx, cy, cell) in g["changes"]:
+            grid[(cx, cy)] = cell
+        want2 = np.array([NO if grid[p] is None else int(grid[p][1:]) for p in pts], dtype=np.uint32)
+        assert np.array_equal(classify_dev(rs, pk), want2)
+    finally:
+        T.tang_ruleset_destroy(rs)
+
+
+def test_exhaustive_restricted_universe():
+    """Rules and packets confined to SIP/DIP top-3 bits, ports 0..7, protocol {6, 17}:
+    all 8,192 packets of that universe against the oracle, probe-all and with models."""
+    torch_cuda()
+    rng = np.random.default_rng(11)
+    n = 120
+    r = np.zeros(n, dtype=synth.RULE_DTYPE)
+    r["sip_len"] = rng.integers(1, 4, n)
+    r["dip_len"] = rng.integers(0, 4, n)
+    r["sip"] = (rng.integers(0, 8, n) << 29).astype(np.uint32)
+    r["dip"] = (rng.integers(0, 8, n) << 29).astype(np.uint32)
+    for f in ("sp", "dp"):
+        a, b = rng.integers(0, 8, n), rng.integers(0, 8, n)
+        wild = rng.random(n) < 0.15
+        r[f + "_lo"] = np.where(wild, 0, np.minimum(a, b))
+        r[f + "_hi"] = np.where(wild, 65535, np.maximum(a, b))
+    pr = rng.choice([6, 17, 17, -1], n)
+    r["proto"] = np.where(pr < 0, 0, pr)
+    r["proto_mask"] = np.where(pr < 0, 0, 255)
+    r["priority"] = rng.integers(0, 100, n)       # many ties -> id order decides
+    r["id"] = rng.permutation(n).astype(np.uint32) + 5
+    grid = np.stack(np.meshgrid(np.arange(8), np.arange(8), np.arange(8), np.arange(8), [6, 17],
+                                indexing="ij"), -1).reshape(-1, 5)
+    pk = np.zeros(len(grid), dtype=synth.HDR_DTYPE)
+    pk["sip"] = (grid[:, 0] << 29).astype(np.uint32)
+    pk["dip"] = (grid[:, 1] << 29).astype(np.uint32)
+    pk["sp"], pk["dp"], pk["proto"] = grid[:, 2], grid[:, 3], grid[:, 4]
+    want = orc.classify(r, pk)
+    assert (want == NO).any() and (want != NO).any()
+    rs = T.tang_ruleset_create(0, r)
+    try:
+        assert np.array_equal(classify_dev(rs, pk), want)
+        C = T.tang_ruleset_num_tuples(rs)
+        for seed in range(3):
+            Ws, bs = train.random_weights(C, 128, seed=seed, scale=3.0)
+            for prec in ("fp32", "bf16"):
+                _load(rs, Ws, bs, prec, topk=1 + seed % 2)
+                assert np.array_equal(classify_dev(rs, pk), want), (seed, prec)
+    finally:
+        T.tang_ruleset_destroy(rs)
+
+
+def test_conflict_masks_equal_bruteforce():
+    torch_cuda()
+    rules = synth.make_rules(400, seed=21, ordering="specificity", mix=0.25)
+    rules["priority"] = np.random.default_rng(0).integers(0, 50, len(rules))  # ties
+    rt = orc.rule_tuples(rules)
+    want = orc.conflict_masks(rules, rt)
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        for k in range(len(rules)):
+            assert T.tang_ruleset_rule_tuple(rs, int(rules[k]["id"])) == rt[k]
+            assert T.tang_ruleset_conflict_mask(rs, int(rules[k]["id"])) == int(want[k]), k
+    finally:
+        T.tang_ruleset_destroy(rs)
+
+
+@pytest.mark.parametrize("ordering", ["specificity", "literal"])
+def test_c1_1k_rules_all_weights_identical(ordering):
+    """1,024 rules, 10,000 headers (70% inside rules), 104 -> 128 -> 128 -> C: rule ids
+    equal the oracle's with no model, trained, random, all-zero and adversarial weights."""
+    torch_cuda()
+    cfg = synth.CONFIGS["c1_1k"]
+    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering=ordering)
+    hdr = synth.make_packets(rules, cfg["n_pkts"], seed=cfg["seed"] + 1, frac_in=cfg["frac_in"])
+    want = orc.classify(rules, hdr)
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        C = T.tang_ruleset_num_tuples(rs)
+        got, st = classify_dev(rs, hdr, stats=True)
+        assert np.array_equal(got, want)
+        assert st["packets"] == len(hdr) and st["fallbacks"] == len(hdr)
+        Ws, bs, sc, acc = train.fit(rs, rules, hdr, 128, steps=2000, seed=1, device="cuda")
+        models = {"trained": (Ws, bs), "random": train.random_weights(C, 128, seed=2),
+                  "zero": train.constant_winner_weights(C, 128, 0)}
+        # adversarial: always predict the tuple holding the fewest answers
+        lab = train.tuple_labels(rs, rules, want)
+        worst = int(np.argmin(np.bincount(lab[lab >= 0], minlength=C)))
+        models["adversarial"] = train.constant_winner_weights(C, 128, worst)
+        for name, (W, b) in models.items():
+            for prec in ("fp32", "bf16", "fp8"):
+                for k in (1, 2):
+                    _load(rs, W, b, prec, topk=k, sc=sc)
+                    got, st = classify_dev(rs, hdr, stats=True)
+                    assert np.array_equal(got, want), (name, prec, k)
+        _load(rs, Ws, bs, "fp32")
+        _, st = classify_dev(rs, hdr, stats=True)
+        assert st["top1_hits"] > 0.5 * len(hdr), st  # the trained model mostly hits
+    finally:
+        T.tang_ruleset_destroy(rs)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_c2_64k_rules_mix(prec):
+    """65,536 rules with the 25% wildcard-heavy mix, 104 -> 256 -> 256 -> C; 200,000 of
+    the configuration's headers compared in full."""
+    torch_cuda()
+    cfg = synth.CONFIGS["c2_64k"]
+    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering="specificity", mix=cfg["mix"])
+    hdr = synth.make_packets(rules, 200_000, seed=cfg["seed"] + 1, frac_in=cfg["frac_in"])
+    want = orc.classify(rules, hdr)
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        assert np.array_equal(classify_dev(rs, hdr), want)
+        Ws, bs, sc, acc = train.fit(rs, rules, hdr[:100_000], 256, steps=300, seed=3,
+                                    rule_ids=want[:100_000], device="cuda")
+        _load(rs, Ws, bs, prec)
+        got, st = classify_dev(rs, hdr, stats=True)
+        assert np.array_equal(got, want)
+        assert st["packets"] == len(hdr) and st["probes"] <= 25 * len(hdr)
+    finally:
+        T.tang_ruleset_destroy(rs)
+
+
+def test_c3_512k_rules_16m_headers_sampled():
+    """512k rules, 16,777,216 Zipf headers, BF16 and FP8, in the launch shape the
+    benchmark times: every answer's key is <= the key of the rule the header was drawn
+    from (an answer at least as good exists) and the answer rule contains the header; a
+    seeded sample of 20,000 answers equals the oracle's."""
+    torch = torch_cuda()
+    cfg = synth.CONFIGS["c3_512k"]
+    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering="specificity")
+    hdr, src = synth.make_packets(rules, cfg["n_pkts"], seed=cfg["seed"] + 1,
+                                  frac_in=cfg["frac_in"], zipf_s=cfg["zipf"], return_src=True)
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        samp = np.random.default_rng(5).choice(len(hdr), 20_000, replace=False)
+        want = orc.classify(rules, hdr[samp])
+        Ws, bs, sc, acc = train.fit(rs, rules, hdr[:200_000], 256, steps=200, seed=4, device="cuda")
+        for prec in ("bf16", "fp8"):
+            _load(rs, Ws, bs, prec, sc=sc)
+            got = classify_dev(rs, hdr)
+            assert np.array_equal(got[samp], want), prec
+            assert (got != NO).all()
+            assert (keys_of(rules, got) <= keys_of(rules, rules["id"][src])).all()
+            for k in samp[:200]:
+                assert orc.rule_matches(rules[int(got[k])], hdr[k])  # id == index here
+        del torch
+    finally:
+        T.tang_ruleset_destroy(rs)
+
+
+def test_empty_and_ragged_batches():
+    torch_cuda()
+    rules = synth.make_rules(2000, seed=31)
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        C = T.tang_ruleset_num_tuples(rs)
+        Ws, bs = train.random_weights(C, 256, seed=3)
+        _load(rs, Ws, bs, "bf16", topk=3)
+        assert len(classify_dev(rs, np.zeros(0, dtype=synth.HDR_DTYPE))) == 0
+        for n in (1, 15, 16, 17, 255, 257, 511, 4097, 33333):
+            hdr = synth.make_packets(rules, n, seed=n, frac_in=0.6)
+            assert np.array_equal(classify_dev(rs, hdr), orc.classify(rules, hdr)), n
+    finally:
+        T.tang_ruleset_destroy(rs)
+
+
+def test_empty_ruleset_answers_no_match():
+    torch_cuda()
+    rs = T.tang_ruleset_create(0, np.zeros(0, dtype=synth.RULE_DTYPE))
+    try:
+        hdr = synth.make_packets(np.zeros(0, dtype=synth.RULE_DTYPE), 1000, seed=1, frac_in=0.0)
+        assert (classify_dev(rs, hdr) == NO).all()
+    finally:
+        T.tang_ruleset_destroy(rs)

@@ -1,0 +1,82 @@
+"""Serving loop: continuous batching over several rulesets. Each request's answers are
+the same whether it runs alone or mixed with others (integer results: tolerance 0), and
+equal the oracle's."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2601_03187_amd import synth, train
+from paper_2601_03187_amd import tang as T
+from tests._gpu import torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _rulesets():
+    out = []
+    for k, (n, prec) in enumerate([(1000, "bf16"), (5000, "fp8"), (20_000, None)]):
+        rules = synth.make_rules(n, seed=600 + k)
+        rs = T.tang_ruleset_create(0, rules)
+        if prec:
+            C = T.tang_ruleset_num_tuples(rs)
+            Ws, bs = train.random_weights(C, 256, seed=k)
+            T.tang_model_load(rs, Ws, bs, prec, act_scales=[1.0, 0.05, 0.05] if prec == "fp8" else None)
+        out.append((rules, rs))
+    return out
+
+
+@pytest.mark.parametrize("graphs,limit", [(1, 0), (0, 0), (1, 20_000)])
+def test_alone_equals_mix(graphs, limit):
+    torch_cuda()
+    sets = _rulesets()
+    srv = T.tang_server_create(0, n_streams=3, max_batch=16384, use_graphs=graphs,
+                               max_inflight_packets=limit)
+    try:
+        tags = [T.tang_server_add_ruleset(srv, rs) for _, rs in sets]
+        rng = np.random.default_rng(graphs * 10 + (limit > 0))
+        reqs = []
+        for q in range(90):
+            tag = int(rng.integers(0, 3))
+            n = int(np.floor(np.exp(rng.uniform(np.log(32), np.log(16384)))))
+            hdr = synth.make_packets(sets[tag][0], n, seed=1000 + q, frac_in=0.8)
+            out = np.full(n, 0xDEADBEEF, dtype=np.uint32)
+            reqs.append((tag, hdr, out, T.tang_server_submit(srv, tags[tag], hdr, out)))
+            if q % 7 == 0:
+                time.sleep(0.001)  # some arrive while others are on the GPU
+        for tag, hdr, out, r in reqs:
+            T.tang_server_wait(r, 60_000_000)
+            s, a, d = T.tang_server_req_times(r)
+            assert 0 < s <= a <= d
+            alone = T.tang_classify_host(sets[tag][1], hdr)
+            assert np.array_equal(out, alone)
+            assert np.array_equal(out, orc.classify(sets[tag][0], hdr))
+            T.tang_server_req_free(r)
+        # an update bumps the ruleset version: graphs are captured again
+        ins = synth.make_rules(50, seed=999, ordering="literal")
+        ins["id"] += 1_000_000
+        ins["priority"] = 0
+        T.tang_insert(sets[0][1], ins)
+        allr = np.concatenate([sets[0][0], ins])
+        hdr = synth.make_packets(allr, 3000, seed=5, frac_in=0.9)
+        out = np.zeros(3000, dtype=np.uint32)
+        r = T.tang_server_submit(srv, tags[0], hdr, out)
+        T.tang_server_wait(r, 60_000_000)
+        assert np.array_equal(out, orc.classify(allr, hdr))
+        T.tang_server_req_free(r)
+        # limits: a request that can never be admitted, and an empty one
+        big = np.zeros(20_000, dtype=synth.HDR_DTYPE)
+        with pytest.raises(T.TangError) as e:
+            T.tang_server_submit(srv, tags[0], big, np.zeros(20_000, dtype=np.uint32))
+        assert e.value.name == "EBUSY"
+        r = T.tang_server_submit(srv, tags[0], np.zeros(0, dtype=synth.HDR_DTYPE), np.zeros(0, dtype=np.uint32))
+        assert T.tang_server_poll(r)
+        T.tang_server_req_free(r)
+        with pytest.raises(T.TangError) as e:
+            T.tang_server_submit(srv, 7, hdr, out)
+        assert e.value.name == "EINVAL"
+    finally:
+        T.tang_server_destroy(srv)
+        for _, rs in sets:
+            T.tang_ruleset_destroy(rs)
