@@ -68,6 +68,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-literal", action="store_true")
+    ap.add_argument("--skip-probe-all", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run a plain device copy of this many bytes (3 times), the "
+                         "reference kernel that calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); classification "
@@ -83,6 +87,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_bytes:
+        a = torch.empty(args.copy_bytes // 4, dtype=torch.int32, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log(f"[bench] copy calibration: 3 x {args.copy_bytes} bytes")
     cfg = synth.CONFIGS["c3_512k"]
     n = cfg["n_pkts"]
     t0 = time.time()
@@ -152,6 +165,22 @@ def main():
             search_bytes_per_pkt=bytes_pkt)
         log(f"[bench] {prec}: {per[prec]['mpps']:.0f} Mpps, mlp {k1:.3f} ms, search {k23:.3f} ms, "
             f"probes/pkt {per[prec]['probes_per_pkt']:.2f}")
+
+    probe_all = None
+    if not args.skip_probe_all:
+        T.tang_model_unload(rs)
+        pst = T.tang_classify(rs, d_hdr, d_out, n, stream, want_stats=True)
+        assert np.array_equal(d_out.cpu().numpy().view(np.uint32), got_by_prec[args.precisions.split(",")[0]])
+        for _ in range(args.warmup):
+            T.tang_classify(rs, d_hdr, d_out, n, stream)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for _ in range(args.steps):
+            T.tang_classify(rs, d_hdr, d_out, n, stream)
+        torch.cuda.synchronize()
+        probe_all = {"mpps": n * args.steps / (time.perf_counter() - w0) / 1e6,
+                     "probes_per_pkt": pst["probes"] / n, "records_per_pkt": pst["records"] / n}
+        log(f"[bench] no model (every tuple, best-key order): {probe_all['mpps']:.0f} Mpps")
 
     # the same answers in every precision; sample checked against the oracle below
     base = args.precisions.split(",")[0]
@@ -246,7 +275,7 @@ def main():
         "bit_exact": exact,
         "roofline": roof, "kernels": other,
         "per_precision": per, "candidate_change_vs_fp32": cand_change,
-        "literal_ordering": lit,
+        "literal_ordering": lit, "no_model_probe_all": probe_all,
         "build_s": build_s, "train_top1": acc,
         "cpu_baseline": cpu,
         "paper_context": "TaNG reports 10.98 Mpps average at 512k rules (12 ClassBench-ng rulesets, "

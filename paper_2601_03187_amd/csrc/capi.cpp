@@ -24,8 +24,9 @@ using namespace tang;
 
 size_t tang_ruleset_s::device_bytes() const {
     if (device == TANG_HOST_ONLY) return 0;
-    return slots.size() * sizeof(Slot) + (size_t)rec_cap * sizeof(Rec) + sizeof(TupleTable) +
-           sizeof(StatsDev) + model.bytes;
+    return slots.size() * sizeof(Slot) + filter.size() * sizeof(uint32_t) +
+           (size_t)rec_cap * sizeof(Rec) + sizeof(TupleTable) +
+           kStatCopies * sizeof(StatsDev) + model.bytes;
 }
 
 #define TANG_GUARD_BEGIN try {
@@ -46,6 +47,8 @@ static void free_device(tang_ruleset_t* rs) {
     hipSetDevice(rs->device);
     model_free(rs->model);
     if (rs->d_slots) hipFree(rs->d_slots);
+    if (rs->d_filter) hipFree(rs->d_filter);
+    rs->d_filter = nullptr;
     if (rs->d_recs) hipFree(rs->d_recs);
     if (rs->d_tt) hipFree(rs->d_tt);
     if (rs->d_stats) hipFree(rs->d_stats);
@@ -179,14 +182,20 @@ static int run_search(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* 
     std::unique_lock<std::mutex> lk(rs->stats_mu, std::defer_lock);
     if (stats) {
         lk.lock();
-        TANG_HIP(hipMemsetAsync(rs->d_stats, 0, sizeof(StatsDev), s));
+        TANG_HIP(hipMemsetAsync(rs->d_stats, 0, kStatCopies * sizeof(StatsDev), s));
     }
     const int kcand = rs->model.loaded ? rs->model.topk : 0;
     TANG_HIP(launch_classify(rs, d_hdr, d_io, n, kcand, s, stats != nullptr));
     if (stats) {
-        StatsDev h;
-        TANG_HIP(hipMemcpyAsync(&h, rs->d_stats, sizeof h, hipMemcpyDeviceToHost, s));
+        StatsDev part[kStatCopies], h;
+        std::memset(&h, 0, sizeof h);
+        TANG_HIP(hipMemcpyAsync(part, rs->d_stats, sizeof part, hipMemcpyDeviceToHost, s));
         TANG_HIP(hipStreamSynchronize(s));
+        for (const StatsDev& p : part) {
+            h.packets += p.packets; h.probes += p.probes; h.slots += p.slots;
+            h.records += p.records; h.top1 += p.top1; h.fallbacks += p.fallbacks;
+            h.nomatch += p.nomatch;
+        }
         stats->packets = h.packets;
         stats->probes = h.probes;
         stats->slots = h.slots;

@@ -7,6 +7,8 @@
 //      remaining tuple (the paper's post-verification search, Sec. 5.1.1);
 //   in both cases tuples are visited in ascending order of their best key and the
 //   search stops once a tuple's best key cannot beat the current answer.
+// Before any slot walk, one bit per tuple from the bucket filter rules out tuples that
+// have no bucket for the header's masked addresses (most certification probes).
 // Candidates come packed in the output word (one byte per candidate) from the MLP.
 #include "tang_internal.hpp"
 
@@ -32,35 +34,74 @@ __device__ __forceinline__ bool rec_match(const Rec& r, uint32_t sip, uint32_t d
     return ok;
 }
 
+// Compares one list of records in (priority, id) order: the first match is its best;
+// the scan stops there or at the first record that cannot beat the current answer.
+template <bool STATS>
+__device__ __forceinline__ void scan_list(uint32_t off, uint32_t len, uint32_t sip, uint32_t dip,
+                                          uint32_t sp, uint32_t dp, uint32_t proto,
+                                          const Rec* __restrict__ recs, Best& b, uint32_t& n_recs) {
+    for (uint32_t k = 0; k < len; ++k) {
+        const Rec r = recs[off + k];
+        if (STATS) ++n_recs;
+        if (!kless(r.prio, r.id, b.prio, b.id)) break;
+        if (rec_match(r, sip, dip, sp, dp, proto)) {
+            b = Best{r.prio, r.id, r.cmask, meta_tuple(r.meta)};
+            break;
+        }
+    }
+}
+
+// Walks the open-addressing slots to key (tk, k0, k1); returns the slot, or an empty one.
+// The table is kept at most a third full, so an empty slot ends every walk; the step
+// bound only guards against a corrupted table.
+template <bool STATS>
+__device__ __forceinline__ Slot find_slot(uint32_t tk, uint32_t k0, uint32_t k1, uint32_t slot_mask,
+                                          const Slot* __restrict__ slots, uint32_t& n_slots) {
+    uint32_t h = slot_of(key_hash(tk, k0, k1)) & slot_mask;
+    for (uint32_t step = 0; step <= slot_mask; ++step) {
+        const Slot s = slots[h];
+        if (STATS) ++n_slots;
+        if (s.tl == kEmptyTL || (s.ms == k0 && s.md == k1 && (s.tl >> 24) == tk)) return s;
+        h = (h + 1) & slot_mask;
+    }
+    return Slot{0, 0, kEmptyTL, 0};
+}
+
 template <bool STATS>
 __device__ __forceinline__ void probe(uint32_t t, uint32_t sip, uint32_t dip, uint32_t sp,
                                       uint32_t dp, uint32_t proto, const TupleDev* s_t,
                                       uint32_t slot_mask, const Slot* __restrict__ slots,
                                       const Rec* __restrict__ recs, Best& b, uint32_t& n_slots,
                                       uint32_t& n_recs) {
-    const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
-    uint32_t h = slot_hash(t, ms, md) & slot_mask;
-    // the table is kept at most half full, so an empty slot ends every walk; the step
-    // bound only guards against a corrupted table
-    for (uint32_t step = 0; step <= slot_mask; ++step) {
-        const Slot s = slots[h];
-        if (STATS) ++n_slots;
-        if (s.tl == kEmptyTL) return;
-        if (s.ms == ms && s.md == md && (s.tl >> 24) == t) {
-            const uint32_t len = s.tl & kMaxBucketLen;
-            for (uint32_t k = 0; k < len; ++k) {
-                const Rec r = recs[s.off + k];
-                if (STATS) ++n_recs;
-                if (!kless(r.prio, r.id, b.prio, b.id)) break;
-                if (rec_match(r, sip, dip, sp, dp, proto)) {
-                    b = Best{r.prio, r.id, r.cmask, meta_tuple(r.meta)};
-                    break;
-                }
-            }
-            return;
-        }
-        h = (h + 1) & slot_mask;
+    const Slot s = find_slot<STATS>(t, sip & s_t[t].smask, dip & s_t[t].dmask, slot_mask, slots, n_slots);
+    if (s.tl == kEmptyTL) return;
+    if (!(s.off & kSplit)) {
+        scan_list<STATS>(s.off, s.tl & kMaxBucketLen, sip, dip, sp, dp, proto, recs, b, n_recs);
+        return;
     }
+    // a split bucket: only the four sub-lists this header's DP, SP and protocol select
+    const uint32_t bi = s.off & ~kSplit;
+    const uint32_t keys[4][2] = {{kSubDp, dp}, {kSubSp, sp}, {kSubProto, proto}, {kSubRest, 0u}};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const Slot u = find_slot<STATS>(t | (keys[q][0] << 5), bi, keys[q][1], slot_mask, slots, n_slots);
+        if (u.tl != kEmptyTL)
+            scan_list<STATS>(u.off, u.tl & kMaxBucketLen, sip, dip, sp, dp, proto, recs, b, n_recs);
+    }
+}
+
+// Tuples whose bucket filter has this header's masked key: every tuple that holds a
+// matching rule is among them. The loads are independent, so they overlap.
+__device__ __forceinline__ uint32_t filter_pass(uint32_t sip, uint32_t dip, uint32_t ntup,
+                                                const TupleDev* s_t, uint32_t filter_mask,
+                                                const uint32_t* __restrict__ filter) {
+    uint32_t f = 0;
+#pragma unroll 8
+    for (uint32_t t = 0; t < ntup; ++t) {
+        const uint32_t bit = filter_of(key_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask)) & filter_mask;
+        f |= ((filter[bit >> 5] >> (bit & 31u)) & 1u) << t;
+    }
+    return f;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
@@ -74,6 +115,7 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                                                   uint32_t* __restrict__ out, uint32_t n,
                                                   const Slot* __restrict__ slots,
                                                   const Rec* __restrict__ recs,
+                                                  const uint32_t* __restrict__ filter,
                                                   const TupleTable* __restrict__ ttg, int kcand,
                                                   StatsDev* __restrict__ st) {
     __shared__ TupleDev s_t[TANG_MAX_TUPLES];
@@ -88,9 +130,11 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
         s_misc[0] = ttg->n;
         s_misc[1] = ttg->all_mask;
         s_misc[2] = ttg->slot_mask;
+        s_misc[3] = ttg->filter_mask;
     }
     __syncthreads();
-    const uint32_t ntup = s_misc[0], all_mask = s_misc[1], slot_mask = s_misc[2];
+    const uint32_t ntup = s_misc[0], all_mask = s_misc[1], slot_mask = s_misc[2],
+                   filter_mask = s_misc[3];
     const uint32_t i = blockIdx.x * 256u + tid;
     uint32_t n_probe = 0, n_slots = 0, n_recs = 0, top1 = 0, fb = 0, nm = 0, active = 0;
     if (i < n) {
@@ -100,9 +144,10 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                        proto = h.w & 0xFFu;
         Best b{kDead, kDead, 0u, 0u};
         bool found = false;
-        uint32_t probed = 0, c0 = 0xFFu;
+        const uint32_t cp = kcand > 0 ? out[i] : 0u;
+        const uint32_t live = filter_pass(sip, dip, ntup, s_t, filter_mask, filter);
+        uint32_t probed = ~live, c0 = 0xFFu;
         if (kcand > 0) {
-            const uint32_t cp = out[i];
             for (int c = 0; c < kcand; ++c) {
                 const uint32_t t = (cp >> (8 * c)) & 0xFFu;
                 if (c == 0) c0 = t;
@@ -133,17 +178,20 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
         }
     }
     if (STATS) {
+        // wave sums -> block sums in LDS -> one set of atomics per block, spread over
+        // kStatCopies counter copies (summed on the host) to avoid one hot address
+        __shared__ unsigned long long s_red[4][7];
         unsigned long long v[7] = {active, n_probe, n_slots, n_recs, top1, fb, nm};
 #pragma unroll
         for (int q = 0; q < 7; ++q) v[q] = wave_sum(v[q]);
-        if ((tid & 63) == 0) {
-            atomicAdd(&st->packets, v[0]);
-            atomicAdd(&st->probes, v[1]);
-            atomicAdd(&st->slots, v[2]);
-            atomicAdd(&st->records, v[3]);
-            atomicAdd(&st->top1, v[4]);
-            atomicAdd(&st->fallbacks, v[5]);
-            atomicAdd(&st->nomatch, v[6]);
+        if ((tid & 63) == 0)
+#pragma unroll
+            for (int q = 0; q < 7; ++q) s_red[tid >> 6][q] = v[q];
+        __syncthreads();
+        if (tid < 7) {
+            const unsigned long long sum = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+            unsigned long long* dst = reinterpret_cast<unsigned long long*>(st + (blockIdx.x % kStatCopies));
+            atomicAdd(dst + tid, sum);
         }
     }
 }
@@ -159,10 +207,10 @@ hipError_t launch_classify(const tang_ruleset_t* rs, const tang_header_t* d_hdr,
         const uint4* h = reinterpret_cast<const uint4*>(d_hdr) + base;
         if (stats)
             hipLaunchKernelGGL(k_classify<true>, grid, block, 0, s, h, d_out + base, m, rs->d_slots,
-                               rs->d_recs, rs->d_tt, kcand, rs->d_stats);
+                               rs->d_recs, rs->d_filter, rs->d_tt, kcand, rs->d_stats);
         else
             hipLaunchKernelGGL(k_classify<false>, grid, block, 0, s, h, d_out + base, m,
-                               rs->d_slots, rs->d_recs, rs->d_tt, kcand, rs->d_stats);
+                               rs->d_slots, rs->d_recs, rs->d_filter, rs->d_tt, kcand, rs->d_stats);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -29,6 +29,20 @@ struct alignas(16) Slot {
 constexpr uint32_t kEmptyTL = 0xFFFFFFFFu;
 constexpr uint32_t kMaxBucketLen = 0x00FFFFFFu;
 
+// Long buckets are split. A bucket that would hold more than kSplitAt rules keeps its
+// slot only as a marker (len 0, off = kSplit | bucket index); its rules move to four
+// sub-lists stored in the same table under keys (tuple | kind << 5, bucket index, value):
+//   kSubDp    rules with an exact DP, value = that DP
+//   kSubSp    rules with an exact SP (DP not exact), value = that SP
+//   kSubProto rules with an exact protocol and no exact port, value = the protocol
+//   kSubRest  every other rule, value 0
+// A header reads the four lists its own DP, SP and protocol select; each list is in
+// (priority, id) order, so the first match of each is its best and the minimum of the
+// four is the bucket's best. Rules that cannot match the header are never scanned.
+constexpr uint32_t kSplit = 0x80000000u;
+constexpr uint32_t kSplitAt = 32;
+enum : uint32_t { kSubDp = 1, kSubSp = 2, kSubProto = 3, kSubRest = 4 };
+
 // Rec (32 B): one rule as the bucket scan reads it. Two 16-byte loads.
 //   sip, dip : prefix values, bits beyond the length zeroed
 //   sp, dp   : lo | hi << 16 (inclusive)
@@ -68,12 +82,13 @@ struct TupleTable {
     uint32_t n;                       // number of tuples
     uint32_t all_mask;                // bits of all tuples
     uint32_t slot_mask;               // slots - 1
-    uint32_t pad;
+    uint32_t filter_mask;             // filter bits - 1
 };
 
-// Slot index: MurmurHash3's 64-bit finaliser (fmix64, Appleby, public domain) over the
-// packed masked addresses, salted by the tuple index (golden-ratio multiple).
-__host__ __device__ inline uint32_t slot_hash(uint32_t t, uint32_t ms, uint32_t md) {
+// Key hash: MurmurHash3's 64-bit finaliser (fmix64, Appleby, public domain) over the
+// packed masked addresses, salted by the tuple index (golden-ratio multiple). The low 32
+// bits pick the slot, the high 32 bits pick the filter bit.
+__host__ __device__ inline uint64_t key_hash(uint32_t t, uint32_t ms, uint32_t md) {
     uint64_t k = ((uint64_t)ms << 32) | md;
     k ^= (uint64_t)(t + 1u) * 0x9E3779B97F4A7C15ull;
     k ^= k >> 33;
@@ -81,13 +96,21 @@ __host__ __device__ inline uint32_t slot_hash(uint32_t t, uint32_t ms, uint32_t 
     k ^= k >> 33;
     k *= 0xC4CEB9FE1A85EC53ull;
     k ^= k >> 33;
-    return (uint32_t)k;
+    return k;
 }
+__host__ __device__ inline uint32_t slot_of(uint64_t h) { return (uint32_t)h; }
+__host__ __device__ inline uint32_t filter_of(uint64_t h) { return (uint32_t)(h >> 32); }
 
-// Device-side counters for tang_stats_t.
+// Bucket filter: one bit per filter_of(key) over all buckets ever created (a superset
+// after deletes). A header's masked key whose bit is clear has no bucket in that tuple,
+// so the slot walk is skipped; at >= 32 bits per bucket about 3% of absent keys pass.
+// Sized to stay L2-resident (2 MB at 512k rules).
+
+// Device-side counters for tang_stats_t (kStatCopies copies, summed on the host).
 struct StatsDev {
     unsigned long long packets, probes, slots, records, top1, fallbacks, nomatch;
 };
+constexpr int kStatCopies = 64;
 
 // Rule box used by the conflict-mask kernels (key order), 32 B.
 struct alignas(16) BoxDev {
@@ -130,10 +153,11 @@ struct tang_ruleset_s {
         bool live;
     };
     struct Bucket {
-        uint32_t t, ms, md;
+        uint32_t t, ms, md;             // t carries the sub-list kind in bits 5-7
         uint32_t slot;
         uint32_t off, cap;
         std::vector<uint32_t> members;  // rule handles in (priority, id) order
+        bool split = false;             // main bucket whose rules live in sub-lists
     };
     struct BKey {
         uint32_t t, ms, md;
@@ -141,7 +165,7 @@ struct tang_ruleset_s {
     };
     struct BKeyHash {
         size_t operator()(const BKey& k) const {
-            return (size_t)tang::slot_hash(k.t, k.ms, k.md);
+            return (size_t)tang::key_hash(k.t, k.ms, k.md);
         }
     };
 
@@ -154,10 +178,12 @@ struct tang_ruleset_s {
     std::vector<Bucket> buckets;
     std::unordered_map<BKey, uint32_t, BKeyHash> bucket_of;
     std::vector<tang::Slot> slots;                 // host mirror of the slot table
+    std::vector<uint32_t> filter;                  // host mirror of the bucket filter
     uint32_t rec_used = 0, rec_cap = 0;
 
     // device state
     tang::Slot* d_slots = nullptr;
+    uint32_t* d_filter = nullptr;
     tang::Rec* d_recs = nullptr;
     tang::TupleTable* d_tt = nullptr;
     tang::StatsDev* d_stats = nullptr;

@@ -17,21 +17,77 @@ uint32_t next_pow2(uint64_t v) {
 
 bool key_less(const tang_rule_t& a, const tang_rule_t& b) { return key_of(a) < key_of(b); }
 
+// Slot contents of bucket b: a split marker, or the bucket's list.
+Slot slot_value(const tang_ruleset_t* rs, uint32_t b) {
+    const auto& bk = rs->buckets[b];
+    if (bk.split) return Slot{bk.ms, bk.md, bk.t << 24, kSplit | b};
+    return Slot{bk.ms, bk.md, (bk.t << 24) | (uint32_t)bk.members.size(), bk.off};
+}
+
 // Linear probing from the hash position to the first empty slot.
-uint32_t slot_insert(std::vector<Slot>& slots, uint32_t t, uint32_t ms, uint32_t md, uint32_t len,
-                     uint32_t off) {
+uint32_t slot_insert(std::vector<Slot>& slots, const Slot& v) {
     uint32_t mask = (uint32_t)slots.size() - 1;
-    uint32_t h = slot_hash(t, ms, md) & mask;
+    uint32_t h = slot_of(key_hash(v.tl >> 24, v.ms, v.md)) & mask;
     while (slots[h].tl != kEmptyTL) h = (h + 1) & mask;
-    slots[h] = Slot{ms, md, (t << 24) | len, off};
+    slots[h] = v;
     return h;
 }
 
-void rebuild_slots(tang_ruleset_t* rs, uint32_t nslots) {
-    rs->slots.assign(nslots, Slot{0, 0, kEmptyTL, 0});
+bool is_main(const tang_ruleset_t::Bucket& bk) { return (bk.t >> 5) == 0; }
+
+// Sub-list key of rule h inside the split main bucket b.
+tang_ruleset_t::BKey sub_key(const tang_ruleset_t* rs, uint32_t b, uint32_t h) {
+    const tang_rule_t& r = rs->rules[h].r;
+    const uint32_t t = rs->buckets[b].t;
+    if (r.dp_lo == r.dp_hi) return {t | (kSubDp << 5), b, r.dp_lo};
+    if (r.sp_lo == r.sp_hi) return {t | (kSubSp << 5), b, r.sp_lo};
+    if (r.proto_mask) return {t | (kSubProto << 5), b, r.proto};
+    return {t | (kSubRest << 5), b, 0u};
+}
+
+uint32_t find_or_add_bucket(tang_ruleset_t* rs, const tang_ruleset_t::BKey& k) {
+    auto it = rs->bucket_of.find(k);
+    if (it != rs->bucket_of.end()) return it->second;
+    const uint32_t b = (uint32_t)rs->buckets.size();
+    rs->buckets.push_back({k.t, k.ms, k.md, 0, 0, 0, {}, false});
+    rs->bucket_of.emplace(k, b);
+    return b;
+}
+
+// Moves the rules of main bucket b into its sub-lists (order kept); returns every
+// bucket whose contents changed (b itself and the sub-lists).
+std::vector<uint32_t> split_bucket(tang_ruleset_t* rs, uint32_t b) {
+    std::vector<uint32_t> touched{b};
+    std::vector<uint32_t> mem;
+    mem.swap(rs->buckets[b].members);
+    rs->buckets[b].split = true;
+    for (uint32_t h : mem) {
+        const uint32_t sb = find_or_add_bucket(rs, sub_key(rs, b, h));
+        auto& sm = rs->buckets[sb].members;
+        auto pos = std::upper_bound(sm.begin(), sm.end(), h, [&](uint32_t a, uint32_t x) {
+            return key_of(rs->rules[a].r) < key_of(rs->rules[x].r);
+        });
+        sm.insert(pos, h);
+        rs->rules[h].bucket = sb;
+        if (std::find(touched.begin(), touched.end(), sb) == touched.end()) touched.push_back(sb);
+    }
+    return touched;
+}
+
+void filter_set(std::vector<uint32_t>& f, uint32_t t, uint32_t ms, uint32_t md) {
+    const uint32_t b = filter_of(key_hash(t, ms, md)) & ((uint32_t)f.size() * 32u - 1u);
+    f[b >> 5] |= 1u << (b & 31u);
+}
+
+// Slot table at load <= 1/4 (short walks) and the bucket filter at >= 32 bits per bucket.
+void rebuild_slots(tang_ruleset_t* rs) {
+    const uint64_t nb = rs->buckets.size();
+    rs->slots.assign(next_pow2(std::max<uint64_t>(1024, 4 * nb + 4)), Slot{0, 0, kEmptyTL, 0});
+    rs->filter.assign(std::max<uint64_t>(2048, next_pow2(32 * nb + 32) / 32), 0u);
     for (uint32_t b = 0; b < rs->buckets.size(); ++b) {
         auto& bk = rs->buckets[b];
-        bk.slot = slot_insert(rs->slots, bk.t, bk.ms, bk.md, (uint32_t)bk.members.size(), bk.off);
+        bk.slot = slot_insert(rs->slots, slot_value(rs, b));
+        if (is_main(bk)) filter_set(rs->filter, bk.t, bk.ms, bk.md);
     }
 }
 
@@ -110,6 +166,7 @@ TupleTable make_tuple_table(const tang_ruleset_t* rs) {
     tt.n = n;
     tt.all_mask = n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u);
     tt.slot_mask = rs->slots.empty() ? 0 : (uint32_t)rs->slots.size() - 1;
+    tt.filter_mask = rs->filter.empty() ? 0 : (uint32_t)rs->filter.size() * 32u - 1u;
     return tt;
 }
 
@@ -153,18 +210,13 @@ int build_host(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
         auto& hr = rs->rules[h];
         uint32_t t = hr.tuple;
         tang_ruleset_s::BKey k{t, hr.r.sip & pmask(rs->sigs[t].first), hr.r.dip & pmask(rs->sigs[t].second)};
-        auto it = rs->bucket_of.find(k);
-        uint32_t b;
-        if (it == rs->bucket_of.end()) {
-            b = (uint32_t)rs->buckets.size();
-            rs->buckets.push_back({k.t, k.ms, k.md, 0, 0, 0, {}});
-            rs->bucket_of.emplace(k, b);
-        } else {
-            b = it->second;
-        }
+        const uint32_t b = find_or_add_bucket(rs, k);
         rs->buckets[b].members.push_back(h);
         hr.bucket = b;
     }
+    const size_t n_main = rs->buckets.size();
+    for (uint32_t b = 0; b < n_main; ++b)
+        if (rs->buckets[b].members.size() > kSplitAt) split_bucket(rs, b);
     // Records: buckets laid out contiguously in creation order (by their best key).
     uint32_t off = 0;
     for (auto& bk : rs->buckets) {
@@ -176,7 +228,7 @@ int build_host(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
     }
     rs->rec_used = off;
     rs->rec_cap = off + std::max<uint32_t>(65536u, off / 4);
-    rebuild_slots(rs, next_pow2(std::max<uint64_t>(1024, 2 * (uint64_t)rs->buckets.size() + 2)));
+    rebuild_slots(rs);
     return TANG_OK;
 }
 
@@ -187,9 +239,12 @@ int upload_all(tang_ruleset_t* rs) {
     TANG_HIP(hipSetDevice(rs->device));
     hipStream_t s = rs->upd_stream;
     TANG_HIP(hipMalloc(&rs->d_slots, rs->slots.size() * sizeof(Slot)));
+    TANG_HIP(hipMalloc(&rs->d_filter, rs->filter.size() * sizeof(uint32_t)));
+    TANG_HIP(hipMemcpy(rs->d_filter, rs->filter.data(), rs->filter.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice));
     TANG_HIP(hipMalloc(&rs->d_recs, (size_t)rs->rec_cap * sizeof(Rec)));
     TANG_HIP(hipMalloc(&rs->d_tt, sizeof(TupleTable)));
-    TANG_HIP(hipMalloc(&rs->d_stats, sizeof(StatsDev)));
+    TANG_HIP(hipMalloc(&rs->d_stats, kStatCopies * sizeof(StatsDev)));
 
     std::vector<Rec> recs(rs->rec_cap, dead_rec());
     for (uint32_t h = 0; h < rs->rules.size(); ++h)
@@ -243,7 +298,7 @@ namespace {
 // `fresh` are handles of rules not yet on the device. Then the slot entries, tuple
 // table, and the conflict masks of the fresh rules are brought up to date.
 int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vector<uint32_t>& fresh,
-          bool rehash) {
+          bool rehash, bool filter_dirty) {
     rs->version++;
     if (rs->device == TANG_HOST_ONLY) return TANG_OK;
     TANG_HIP(hipSetDevice(rs->device));
@@ -309,8 +364,7 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
             dst.push_back(old_off + i);
             newrecs.push_back(dead_rec());
         }
-        rs->slots[bk.slot].tl = (bk.t << 24) | len;
-        rs->slots[bk.slot].off = bk.off;
+        rs->slots[bk.slot] = slot_value(rs, b);
         touched_slots.push_back(bk.slot);
     }
 
@@ -344,15 +398,25 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
     if (e == hipSuccess) {
         if (rehash) {
             Slot* ns = nullptr;
+            uint32_t* nf = nullptr;
             e = hipStreamSynchronize(s);
             if (e == hipSuccess) e = hipMalloc(&ns, rs->slots.size() * sizeof(Slot));
+            if (e == hipSuccess) e = hipMalloc(&nf, rs->filter.size() * sizeof(uint32_t));
             if (e == hipSuccess)
                 e = hipMemcpyAsync(ns, rs->slots.data(), rs->slots.size() * sizeof(Slot),
+                                   hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(nf, rs->filter.data(), rs->filter.size() * sizeof(uint32_t),
                                    hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e == hipSuccess) {
                 hipFree(rs->d_slots);
+                hipFree(rs->d_filter);
                 rs->d_slots = ns;
+                rs->d_filter = nf;
+            } else {
+                if (ns) hipFree(ns);
+                if (nf) hipFree(nf);
             }
         } else if (!touched_slots.empty()) {
             std::sort(touched_slots.begin(), touched_slots.end());
@@ -366,6 +430,9 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
             if (e == hipSuccess)
                 e = launch_scatter_slots(rs->d_slots, (const uint32_t*)d_idx, (const Slot*)d_val,
                                          (uint32_t)vals.size(), s);
+            if (e == hipSuccess && filter_dirty)
+                e = hipMemcpyAsync(rs->d_filter, rs->filter.data(),
+                                   rs->filter.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
         }
     }
     TupleTable tt = make_tuple_table(rs);
@@ -424,39 +491,40 @@ int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
         rs->tuple_best[t] = std::min(rs->tuple_best[t], key_of(r));
         tang_ruleset_s::BKey k{(uint32_t)t, r.sip & pmask(rs->sigs[t].first),
                                r.dip & pmask(rs->sigs[t].second)};
-        auto it = rs->bucket_of.find(k);
-        uint32_t b;
-        if (it == rs->bucket_of.end()) {
-            b = (uint32_t)rs->buckets.size();
-            rs->buckets.push_back({k.t, k.ms, k.md, 0, 0, 0, {}});
-            rs->bucket_of.emplace(k, b);
-            if (b >= mark.size()) mark.resize(b + 1, 0);
-        } else {
-            b = it->second;
-        }
+        const uint32_t mb = find_or_add_bucket(rs, k);
+        const uint32_t b = rs->buckets[mb].split ? find_or_add_bucket(rs, sub_key(rs, mb, h)) : mb;
+        if (rs->buckets.size() > mark.size()) mark.resize(rs->buckets.size() + n, 0);
         auto& mem = rs->buckets[b].members;
         auto pos = std::upper_bound(mem.begin(), mem.end(), h, [&](uint32_t a, uint32_t x) {
             return key_of(rs->rules[a].r) < key_of(rs->rules[x].r);
         });
         mem.insert(pos, h);
         rs->rules[h].bucket = b;
-        if (!mark[b]) { mark[b] = 1; dirty.push_back(b); }
+        std::vector<uint32_t> changed{b};
+        if (b == mb && mem.size() > kSplitAt) changed = split_bucket(rs, mb);
+        if (rs->buckets.size() > mark.size()) mark.resize(rs->buckets.size() + n, 0);
+        for (uint32_t c : changed)
+            if (!mark[c]) { mark[c] = 1; dirty.push_back(c); }
         fresh.push_back(h);
     }
     // new buckets need slots; grow the table when it would pass half full
-    bool rehash = false;
+    bool rehash = false, filter_dirty = false;
     if (rs->buckets.size() != nb_before) {
-        if (2 * rs->buckets.size() + 2 > rs->slots.size()) {
-            rebuild_slots(rs, next_pow2(4 * (uint64_t)rs->buckets.size()));
+        // keep the slot table at most 1/3 full and the filter at >= 16 bits per bucket
+        if (3 * rs->buckets.size() + 3 > rs->slots.size() ||
+            16 * rs->buckets.size() > rs->filter.size() * 32) {
+            rebuild_slots(rs);
             rehash = true;
         } else {
             for (size_t b = nb_before; b < rs->buckets.size(); ++b) {
                 auto& bk = rs->buckets[b];
-                bk.slot = slot_insert(rs->slots, bk.t, bk.ms, bk.md, 0, 0);
+                bk.slot = slot_insert(rs->slots, Slot{bk.ms, bk.md, bk.t << 24, 0});
+                if (is_main(bk)) filter_set(rs->filter, bk.t, bk.ms, bk.md);
             }
+            filter_dirty = true;
         }
     }
-    return flush(rs, dirty, fresh, rehash);
+    return flush(rs, dirty, fresh, rehash, filter_dirty);
 }
 
 int apply_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n) {
@@ -479,7 +547,7 @@ int apply_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n) {
         rs->n_live--;
         if (!mark[hr.bucket]) { mark[hr.bucket] = 1; dirty.push_back(hr.bucket); }
     }
-    return flush(rs, dirty, {}, false);
+    return flush(rs, dirty, {}, false, false);
 }
 
 }  // namespace tang

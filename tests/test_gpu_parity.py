@@ -217,3 +217,50 @@ def test_empty_ruleset_answers_no_match():
         assert (classify_dev(rs, hdr) == NO).all()
     finally:
         T.tang_ruleset_destroy(rs)
+
+
+def test_split_buckets_build_and_updates():
+    """Thousands of rules under one (SIP, DIP) prefix pair: the bucket is kept as four
+    sub-lists (exact DP, exact SP, exact protocol, rest). Answers equal the oracle's at
+    build, after inserts and deletes into the sub-lists, and after a second bucket grows
+    past the split threshold through inserts."""
+    torch_cuda()
+    rng = np.random.default_rng(8)
+    rules = synth.make_rules(6000, seed=61, ordering="literal")
+    rules["sip"], rules["sip_len"] = 0x0A000000, 8
+    rules["dip"], rules["dip_len"] = 0, 0
+    rules["priority"] = rng.integers(0, 3000, len(rules))       # ties -> ids decide
+    others = synth.make_rules(3000, seed=62, ordering="specificity")
+    others["id"] += 100_000
+    others["priority"] += 1_000
+    allr = np.concatenate([rules, others])
+    pk = synth.make_packets(allr, 60_000, seed=63, frac_in=0.9)
+    pk["sip"][:30_000] = (pk["sip"][:30_000] & 0x00FFFFFF) | 0x0A000000  # aim at the big bucket
+    pk["proto"][:5000] = rng.choice([6, 17, 1, 141, 0], 5000)
+    rs = T.tang_ruleset_create(0, allr)
+    try:
+        got, st = classify_dev(rs, pk, stats=True)
+        assert np.array_equal(got, orc.classify(allr, pk))
+        assert st["records"] < 60 * len(pk), st    # no header walks the whole bucket
+        ins = synth.make_rules(500, seed=64, ordering="literal")
+        ins["sip"], ins["sip_len"] = 0x0A000000, 8
+        ins["dip"], ins["dip_len"] = 0, 0
+        ins["id"] = np.arange(200_000, 200_500, dtype=np.uint32)
+        ins["priority"] = rng.integers(0, 3000, 500)
+        grow = synth.make_rules(40, seed=65, ordering="literal")   # a second bucket grows past 32
+        grow["sip"], grow["sip_len"] = 0xC0A80000, 16
+        grow["dip"], grow["dip_len"] = 0x0A0A0A00, 24
+        grow["id"] = np.arange(300_000, 300_040, dtype=np.uint32)
+        T.tang_insert(rs, ins)
+        T.tang_insert(rs, grow)
+        dels = rng.choice(rules["id"], 800, replace=False)
+        T.tang_delete(rs, dels)
+        allr2 = np.concatenate([allr, ins, grow])
+        live = ~np.isin(allr2["id"], dels)
+        pk2 = synth.make_packets(allr2[live], 60_000, seed=66, frac_in=0.9)
+        pk2["sip"][:20_000] = (pk2["sip"][:20_000] & 0x00FFFFFF) | 0x0A000000
+        pk2["sip"][20_000:25_000] = (pk2["sip"][20_000:25_000] & 0xFFFF) | 0xC0A80000
+        pk2["dip"][20_000:25_000] = (pk2["dip"][20_000:25_000] & 0xFF) | 0x0A0A0A00
+        assert np.array_equal(classify_dev(rs, pk2), orc.classify(allr2, pk2, live=live))
+    finally:
+        T.tang_ruleset_destroy(rs)
