@@ -69,6 +69,11 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-literal", action="store_true")
     ap.add_argument("--skip-probe-all", action="store_true")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
+                    help="c3: 512k rules / 16M headers (the headline line); c4: the update "
+                         "stream on the 512k ruleset; c5: the serving loop over three rulesets")
+    ap.add_argument("--rounds", type=int, default=100, help="c4: update rounds")
+    ap.add_argument("--requests", type=int, default=2000, help="c5: requests per load level")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run a plain device copy of this many bytes (3 times), the "
                          "reference kernel that calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -87,6 +92,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.workload == "c4":
+        return bench_updates(args)
+    if args.workload == "c5":
+        return bench_serving(args)
     if args.copy_bytes:
         a = torch.empty(args.copy_bytes // 4, dtype=torch.int32, device=dev).fill_(1)
         b = torch.empty_like(a)
@@ -283,6 +292,159 @@ def main():
     }
     print(json.dumps(line), flush=True)
     T.tang_ruleset_destroy(rs)
+
+
+
+def bench_updates(args):
+    """c4: the 512k ruleset under 100 rounds of (100 inserts + 100 deletes), each followed
+    by a 1M-header lookup batch from the live rules; fixed BF16 weights. Per round: the
+    update latency (host + device, synchronised), lookup Mpps, and answers on a seeded
+    sample of the batch against the oracle's re-scan of the live rules."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as orc
+    from paper_2601_03187_amd import synth, train
+    from paper_2601_03187_amd import tang as T
+
+    cfg = synth.CONFIGS["c4_512k_updates"]
+    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering="specificity")
+    rs = T.tang_ruleset_create(0, rules)
+    h0 = synth.make_packets(rules, 1 << 18, seed=cfg["seed"] + 1, frac_in=cfg["frac_in"])
+    Ws, bs, sc, acc = train.fit(rs, rules, h0, cfg["hidden"], steps=args.train_steps, seed=1, device="cuda")
+    T.tang_model_load(rs, Ws, bs, "bf16", topk=1)
+    ups = synth.make_update_stream(rules, args.rounds, cfg["per_round"], seed=cfg["seed"] + 2,
+                                   prio_range=len(rules))
+    all_rules = [rules]
+    live = np.ones(len(rules), dtype=bool)
+    id_pos = {int(i): k for k, i in enumerate(rules["id"])}
+    n = cfg["n_pkts"]
+    d_out = torch.empty(n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    lat, mpps, mism, checked = [], [], 0, 0
+    for rd, (ins, dels) in enumerate(ups):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T.tang_insert(rs, ins)
+        T.tang_delete(rs, dels)
+        lat.append((time.perf_counter() - t0) * 1e3)
+        base = sum(len(a) for a in all_rules)
+        all_rules.append(ins)
+        live = np.concatenate([live, np.ones(len(ins), dtype=bool)])
+        for k, i in enumerate(ins["id"]):
+            id_pos[int(i)] = base + k
+        for i in dels:
+            live[id_pos[int(i)]] = False
+        cat = np.concatenate(all_rules)
+        hdr = synth.make_packets(cat[live], n, seed=cfg["seed"] + 100 + rd, frac_in=cfg["frac_in"])
+        d_hdr = torch.from_numpy(hdr.view(np.uint8).reshape(-1)).cuda()
+        T.tang_classify(rs, d_hdr, d_out, n, stream)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        T.tang_classify(rs, d_hdr, d_out, n, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        mpps.append(n / a.elapsed_time(b) / 1e3)
+        got = d_out.cpu().numpy().view(np.uint32)
+        samp = np.random.default_rng(rd).choice(n, 2000, replace=False)
+        mism += int((orc.classify(cat, hdr[samp], live=live) != got[samp]).sum())
+        checked += len(samp)
+        if rd % 10 == 0:
+            log(f"[bench c4] round {rd}: update {lat[-1]:.2f} ms, lookup {mpps[-1]:.0f} Mpps")
+    st = T.tang_classify(rs, d_hdr, d_out, n, stream, want_stats=True)
+    line = {"metric": "c4 update stream at 512k rules (1 MI355X)", "value": float(np.mean(mpps)),
+            "unit": "Mpps", "n_gpus": 1, "higher_is_better": True, "dtype": "bf16",
+            "data": "synthetic",
+            "config": {"workload": "c4_512k_updates: 524,288 rules, %d rounds x (100 inserts + 100 "
+                                   "deletes) + 1M-header lookups" % args.rounds},
+            "update_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat),
+                          "per": "100 inserts + 100 deletes, synchronised"},
+            "lookup_mpps": {"first": mpps[0], "last": mpps[-1], "min": min(mpps)},
+            "last_round": {"probes_per_pkt": st["probes"] / n, "records_per_pkt": st["records"] / n,
+                           "top1_hit_rate": st["top1_hits"] / n},
+            "bit_exact": {"sample_per_round": 2000, "checked": checked, "mismatches": mism,
+                          "bit_exact": mism == 0}}
+    print(json.dumps(line), flush=True)
+    T.tang_ruleset_destroy(rs)
+
+
+def bench_serving(args):
+    """c5: three device-resident rulesets (10k, 100k, 512k rules, BF16 predictors) behind
+    the serving loop; requests of log-uniform size 32..65,536 with a uniform ruleset tag.
+    First a burst measures saturation; then Poisson arrivals at 25/50/75/90% of it report
+    p50/p99 request latency (submit -> results on the host) and delivered Mpps. A sample of
+    requests is checked against the same headers classified alone."""
+    import numpy as np
+    import torch
+
+    from paper_2601_03187_amd import synth, train
+    from paper_2601_03187_amd import tang as T
+
+    cfg = synth.CONFIGS["c5_serving"]
+    sets = []
+    for k, n_rules in enumerate(cfg["sizes"]):
+        rules = synth.make_rules(n_rules, seed=cfg["seed"] + k, ordering="specificity")
+        rs = T.tang_ruleset_create(0, rules)
+        pool = synth.make_packets(rules, 1 << 21, seed=cfg["seed"] + 10 + k, frac_in=cfg["frac_in"])
+        Ws, bs, sc, acc = train.fit(rs, rules, pool[: 1 << 17], cfg["hidden"], steps=args.train_steps // 2,
+                                    seed=k, device="cuda")
+        T.tang_model_load(rs, Ws, bs, "bf16", topk=1)
+        sets.append((rules, rs, pool))
+    log("[bench c5] rulesets ready")
+    srv = T.tang_server_create(0, n_streams=4, max_batch=65536, use_graphs=1)
+    tags = [T.tang_server_add_ruleset(srv, rs) for _, rs, _ in sets]
+
+    def run(n_req, rate, seed):
+        t_arr, sizes, tg = synth.make_requests(n_req, len(sets), seed=seed, rate_per_s=rate or 1.0)
+        rng = np.random.default_rng(seed)
+        reqs = []
+        t0 = time.perf_counter()
+        for q in range(n_req):
+            if rate:
+                while time.perf_counter() - t0 < t_arr[q]:
+                    pass
+            pool = sets[tg[q]][2]
+            off = int(rng.integers(0, len(pool) - sizes[q]))
+            hdr = pool[off: off + sizes[q]]
+            out = np.empty(sizes[q], dtype=np.uint32)
+            reqs.append((tg[q], hdr, out, T.tang_server_submit(srv, tags[tg[q]], hdr, out)))
+        for _, _, _, r in reqs:
+            T.tang_server_wait(r, 120_000_000)
+        times = [T.tang_server_req_times(r) for *_, r in reqs]
+        first = min(t[0] for t in times)
+        last = max(t[2] for t in times)
+        lat = [(d - s) / 1e6 for s, a, d in times]
+        pk = int(sum(sizes))
+        return reqs, {"requests": n_req, "packets": pk, "mpps": pk / ((last - first) / 1e9) / 1e6,
+                      "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                      "offered_req_per_s": rate, "submit_s": time.perf_counter() - t0}
+
+    run(200, 0, seed=1)  # warm-up: graph capture for the size classes
+    reqs, sat = run(args.requests, 0, seed=2)
+    mean_size = sat["packets"] / sat["requests"]
+    sat_rate = sat["mpps"] * 1e6 / mean_size
+    levels = {}
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        reqs, r = run(args.requests, frac * sat_rate, seed=int(frac * 100))
+        levels[f"{int(frac * 100)}%"] = r
+        log(f"[bench c5] load {frac:.0%}: p50 {r['p50_ms']:.3f} ms p99 {r['p99_ms']:.3f} ms, {r['mpps']:.0f} Mpps")
+    bad = 0
+    for tag, hdr, out, r in reqs[:50]:
+        bad += int((T.tang_classify_host(sets[tag][1], hdr) != out).sum())
+    for *_, r in reqs:
+        T.tang_server_req_free(r)
+    line = {"metric": "c5 serving: p50/p99 request latency and Mpps (1 MI355X)",
+            "value": levels["75%"]["p99_ms"], "unit": "ms (p99 at 75% load)", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": "c5_serving: rulesets of 10k/100k/512k rules, Poisson requests, "
+                                   "sizes log-uniform 32..65536, 4 streams, HIP graphs"},
+            "saturation": sat, "loads": levels,
+            "alone_vs_mix": {"requests_checked": 50, "mismatches": bad}}
+    print(json.dumps(line), flush=True)
+    T.tang_server_destroy(srv)
+    for _, rs, _ in sets:
+        T.tang_ruleset_destroy(rs)
 
 
 if __name__ == "__main__":

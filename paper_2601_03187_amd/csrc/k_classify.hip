@@ -7,8 +7,9 @@
 //      remaining tuple (the paper's post-verification search, Sec. 5.1.1);
 //   in both cases tuples are visited in ascending order of their best key and the
 //   search stops once a tuple's best key cannot beat the current answer.
-// Before any slot walk, one bit per tuple from the bucket filter rules out tuples that
-// have no bucket for the header's masked addresses (most certification probes).
+// Before any slot walk, a bit of the bucket filter rules out a tuple that has no bucket
+// for the header's masked addresses (most certification probes); the bit is read only for
+// tuples the search actually reaches.
 // Candidates come packed in the output word (one byte per candidate) from the MLP.
 #include "tang_internal.hpp"
 
@@ -54,10 +55,14 @@ __device__ __forceinline__ void scan_list(uint32_t off, uint32_t len, uint32_t s
 // Walks the open-addressing slots to key (tk, k0, k1); returns the slot, or an empty one.
 // The table is kept at most a third full, so an empty slot ends every walk; the step
 // bound only guards against a corrupted table.
+// Walks the open-addressing slots from hash h to key (tk, k0, k1); returns the slot, or
+// an empty one. The table is kept at most a third full, so an empty slot ends every
+// walk; the step bound only guards against a corrupted table.
 template <bool STATS>
-__device__ __forceinline__ Slot find_slot(uint32_t tk, uint32_t k0, uint32_t k1, uint32_t slot_mask,
-                                          const Slot* __restrict__ slots, uint32_t& n_slots) {
-    uint32_t h = slot_of(key_hash(tk, k0, k1)) & slot_mask;
+__device__ __forceinline__ Slot find_slot(uint64_t h64, uint32_t tk, uint32_t k0, uint32_t k1,
+                                          uint32_t slot_mask, const Slot* __restrict__ slots,
+                                          uint32_t& n_slots) {
+    uint32_t h = slot_of(h64) & slot_mask;
     for (uint32_t step = 0; step <= slot_mask; ++step) {
         const Slot s = slots[h];
         if (STATS) ++n_slots;
@@ -67,13 +72,22 @@ __device__ __forceinline__ Slot find_slot(uint32_t tk, uint32_t k0, uint32_t k1,
     return Slot{0, 0, kEmptyTL, 0};
 }
 
+// Searches tuple t for this header. One hash serves the filter bit (is there a bucket
+// for the header's masked key at all?) and the slot walk.
 template <bool STATS>
 __device__ __forceinline__ void probe(uint32_t t, uint32_t sip, uint32_t dip, uint32_t sp,
                                       uint32_t dp, uint32_t proto, const TupleDev* s_t,
-                                      uint32_t slot_mask, const Slot* __restrict__ slots,
-                                      const Rec* __restrict__ recs, Best& b, uint32_t& n_slots,
+                                      uint32_t slot_mask, uint32_t filter_mask,
+                                      const uint32_t* __restrict__ filter,
+                                      const Slot* __restrict__ slots, const Rec* __restrict__ recs,
+                                      Best& b, uint32_t& n_probe, uint32_t& n_slots,
                                       uint32_t& n_recs) {
-    const Slot s = find_slot<STATS>(t, sip & s_t[t].smask, dip & s_t[t].dmask, slot_mask, slots, n_slots);
+    const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
+    const uint64_t h = key_hash(t, ms, md);
+    const uint32_t bit = filter_of(h) & filter_mask;
+    if (!((filter[bit >> 5] >> (bit & 31u)) & 1u)) return;
+    if (STATS) ++n_probe;
+    const Slot s = find_slot<STATS>(h, t, ms, md, slot_mask, slots, n_slots);
     if (s.tl == kEmptyTL) return;
     if (!(s.off & kSplit)) {
         scan_list<STATS>(s.off, s.tl & kMaxBucketLen, sip, dip, sp, dp, proto, recs, b, n_recs);
@@ -84,24 +98,12 @@ __device__ __forceinline__ void probe(uint32_t t, uint32_t sip, uint32_t dip, ui
     const uint32_t keys[4][2] = {{kSubDp, dp}, {kSubSp, sp}, {kSubProto, proto}, {kSubRest, 0u}};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const Slot u = find_slot<STATS>(t | (keys[q][0] << 5), bi, keys[q][1], slot_mask, slots, n_slots);
+        const uint32_t tk = t | (keys[q][0] << 5);
+        const Slot u = find_slot<STATS>(key_hash(tk, bi, keys[q][1]), tk, bi, keys[q][1], slot_mask,
+                                        slots, n_slots);
         if (u.tl != kEmptyTL)
             scan_list<STATS>(u.off, u.tl & kMaxBucketLen, sip, dip, sp, dp, proto, recs, b, n_recs);
     }
-}
-
-// Tuples whose bucket filter has this header's masked key: every tuple that holds a
-// matching rule is among them. The loads are independent, so they overlap.
-__device__ __forceinline__ uint32_t filter_pass(uint32_t sip, uint32_t dip, uint32_t ntup,
-                                                const TupleDev* s_t, uint32_t filter_mask,
-                                                const uint32_t* __restrict__ filter) {
-    uint32_t f = 0;
-#pragma unroll 8
-    for (uint32_t t = 0; t < ntup; ++t) {
-        const uint32_t bit = filter_of(key_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask)) & filter_mask;
-        f |= ((filter[bit >> 5] >> (bit & 31u)) & 1u) << t;
-    }
-    return f;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
@@ -145,8 +147,7 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
         Best b{kDead, kDead, 0u, 0u};
         bool found = false;
         const uint32_t cp = kcand > 0 ? out[i] : 0u;
-        const uint32_t live = filter_pass(sip, dip, ntup, s_t, filter_mask, filter);
-        uint32_t probed = ~live, c0 = 0xFFu;
+        uint32_t probed = 0, c0 = 0xFFu;
         if (kcand > 0) {
             for (int c = 0; c < kcand; ++c) {
                 const uint32_t t = (cp >> (8 * c)) & 0xFFu;
@@ -154,9 +155,8 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                 if (t >= ntup || ((probed >> t) & 1u)) continue;
                 probed |= 1u << t;
                 if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) continue;
-                if (STATS) ++n_probe;
-                probe<STATS>(t, sip, dip, sp, dp, proto, s_t, slot_mask, slots, recs, b, n_slots,
-                             n_recs);
+                probe<STATS>(t, sip, dip, sp, dp, proto, s_t, slot_mask, filter_mask, filter, slots,
+                             recs, b, n_probe, n_slots, n_recs);
             }
             found = b.id != kDead || b.prio != kDead;
         }
@@ -167,8 +167,8 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
             if (!((todo >> t) & 1u)) continue;
             if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) break;
             todo &= ~(1u << t);
-            if (STATS) ++n_probe;
-            probe<STATS>(t, sip, dip, sp, dp, proto, s_t, slot_mask, slots, recs, b, n_slots, n_recs);
+            probe<STATS>(t, sip, dip, sp, dp, proto, s_t, slot_mask, filter_mask, filter, slots, recs,
+                         b, n_probe, n_slots, n_recs);
         }
         found = b.id != kDead || b.prio != kDead;
         out[i] = found ? b.id : TANG_NO_MATCH;

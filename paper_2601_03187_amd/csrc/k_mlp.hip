@@ -1,6 +1,7 @@
 // Tuple predictor on MFMA: the plain MLP of Sec. 6.1 (FC -> ReLU -> FC -> ReLU -> FC,
 // 104 -> H -> H -> C) followed by argmax / top-k over the C tuple scores (Sec. 6.1,
-// Sec. 5.1.1), for FP32, BF16 and FP8 (OCP E4M3) operands with FP32 accumulation.
+// Sec. 5.1.1), for FP32, BF16 and FP8 (OCP E4M3) operands with FP32 accumulation:
+// v_mfma_f32_16x16x4_f32, v_mfma_f32_16x16x32_bf16 and v_mfma_f32_16x16x32_fp8_fp8.
 //
 // Orientation: every layer computes out^T = W * in^T with output neurons as MFMA rows
 // (the A operand, weights) and packets as MFMA columns (the B operand, activations).
@@ -28,11 +29,12 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float fl2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
 
 template <int PREC> struct FragT;
 template <> struct FragT<TANG_FP32> { using T = float; static constexpr int KB = 4; };
 template <> struct FragT<TANG_BF16> { using T = u32x4; static constexpr int KB = 32; };
-template <> struct FragT<TANG_FP8> { using T = u32x2; static constexpr int KB = 32; };
+template <> struct FragT<TANG_FP8> { using T = u32x8; static constexpr int KB = 128; };
 
 struct MlpArgs {
     int n_out;
@@ -50,9 +52,16 @@ __device__ __forceinline__ f4 mma(u32x4 a, u32x4 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
-__device__ __forceinline__ f4 mma(u32x2 a, u32x2 b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a),
-                                                      __builtin_bit_cast(long, b), c, 0, 0, 0);
+// FP8 (E4M3) x FP8 over a K = 128 block, as four K = 32 MFMAs on matching quarters of
+// the A and B fragments (the single-instruction K = 128 form,
+// v_mfma_scale_f32_16x16x128_f8f6f4, needs far more registers in this kernel).
+__device__ __forceinline__ f4 mma(u32x8 a, u32x8 b, f4 c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(
+            __builtin_bit_cast(long, (u32x2){a[2 * q], a[2 * q + 1]}),
+            __builtin_bit_cast(long, (u32x2){b[2 * q], b[2 * q + 1]}), c, 0, 0, 0);
+    return c;
 }
 
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
@@ -92,15 +101,18 @@ template <> struct Bits<TANG_BF16> {
     }
 };
 template <> struct Bits<TANG_FP8> {
-    __device__ static __forceinline__ u32x2 get(const uint4& h, int kb, int g) {
-        const uint32_t byte = (hword(h, kb) >> (24 - 8 * g)) & 0xFFu;
-        u32x2 r;
+    // K = 128 in one block: features 32g + j (j = 0..31) are the bits of header word g,
+    // most significant first; 1.0 in E4M3 is 0x38
+    __device__ static __forceinline__ u32x8 get(const uint4& h, int, int g) {
+        const uint32_t w = g == 0 ? h.x : g == 1 ? h.y : g == 2 ? ((h.z << 16) | (h.z >> 16))
+                                                                : ((h.w & 0xFFu) << 24);
+        u32x8 r;
 #pragma unroll
-        for (int w = 0; w < 2; ++w) {
+        for (int q = 0; q < 8; ++q) {
             uint32_t v = 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v |= ((byte >> (7 - (4 * w + q))) & 1u) * (0x38u << (8 * q));
-            r[w] = v;
+            for (int b = 0; b < 4; ++b) v |= ((w >> (31 - (4 * q + b))) & 1u) * (0x38u << (8 * b));
+            r[q] = v;
         }
         return r;
     }
@@ -118,11 +130,16 @@ __device__ __forceinline__ u32x2 bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uin
 __device__ __forceinline__ u32x4 bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, u32x4*) {
     return __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0);
 }
+__device__ __forceinline__ u32x8 bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, u32x8*) {
+    const u32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0);
+    const u32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(r, v + 16, s, 0);
+    return (u32x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
 
 template <bool IN_LDS, typename F>
 __device__ __forceinline__ F ldf(const F* lds, __amdgpu_buffer_rsrc_t r, uint32_t frag, uint32_t lane,
                                  uint32_t sbase) {
-    if constexpr (IN_LDS) return lds[frag * 64 + lane];
+    if constexpr (IN_LDS) return lds[frag * 64 + lane + sbase];  // sbase: opaque 0, see below
     else return bload(r, lane * (uint32_t)sizeof(F) + sbase, frag * 64u * (uint32_t)sizeof(F), (F*)nullptr);
 }
 
@@ -149,17 +166,16 @@ __device__ __forceinline__ void epi_hidden(const f4 (&acc)[NT], int mt, const fl
             dst[mt >> 1][nt][2 * (mt & 1)] = pack_bf16(v[0], v[1]);
             dst[mt >> 1][nt][2 * (mt & 1) + 1] = pack_bf16(v[2], v[3]);
         } else {
+            // a 128-wide K block holds the rows of 8 consecutive output tiles
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = fminf(v[r] * inv_next, 448.0f);
-            dst[mt >> 1][nt][mt & 1] = pack_fp8(v[0], v[1], v[2], v[3]);
+            dst[mt >> 3][nt][mt & 7] = pack_fp8(v[0], v[1], v[2], v[3]);
         }
     }
 }
 
-constexpr int kWaves = 8;
-
-template <int PREC, int H, int NT, int LDSM>
-__global__ __launch_bounds__(64 * kWaves) void k_mlp(
+template <int PREC, int H, int NT, int LDSM, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_mlp(
     const uint4* __restrict__ hdr, uint32_t n, const typename FragT<PREC>::T* __restrict__ w1,
     const typename FragT<PREC>::T* __restrict__ w2, const typename FragT<PREC>::T* __restrict__ w3,
     const float* __restrict__ bias_g, MlpArgs a, uint32_t* __restrict__ cand,
@@ -171,6 +187,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp(
     constexpr int KBN1_USED = PREC == TANG_FP32 ? 104 / KB : KBN1;
     constexpr uint32_t n1 = MTH * KBN1 * 64, n2 = MTH * KBNH * 64, n3 = 2 * KBNH * 64;
     constexpr uint32_t nb = 2 * H + kOutPad;
+    // output tiles per MFMA group in layer 2 (more when each tile is only 1-2 MFMAs)
+    constexpr int TG = PREC == TANG_FP8 ? 4 : PREC == TANG_BF16 ? 2 : 1;
 
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     F* s1 = reinterpret_cast<F*>(smem);
@@ -197,10 +215,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp(
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
     const uint32_t tiles = (n + 16 * NT - 1) / (16 * NT);
     const int C = a.n_out;
-    for (uint32_t tile = blockIdx.x * kWaves + wave; tile < tiles; tile += gridDim.x * kWaves) {
+    for (uint32_t tile = blockIdx.x * WAVES + wave; tile < tiles; tile += gridDim.x * WAVES) {
         const uint32_t pbase = tile * 16u * NT;
-        // the weight loads are loop-invariant; hide that from LICM, which would otherwise
-        // hoist every fragment of the global-resident layers out of the tile loop
+        // the weight loads (LDS and global) are loop-invariant; an opaque zero in their
+        // addresses hides that from LICM, which would otherwise hoist every fragment out
+        // of the tile loop and run out of registers
         uint32_t sbase = 0;
         asm volatile("" : "+s"(sbase));
         uint4 hv[NT];
@@ -209,37 +228,75 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp(
             const uint32_t p = pbase + nt * 16 + col;
             hv[nt] = p < n ? hdr[p] : make_uint4(0, 0, 0, 0);
         }
-        // layer 1: bits -> H
+        // layer 1: bits -> H. When its fragments come from L2 (not LDS), the next tile's
+        // loads are issued before this tile's MFMAs so their latency is hidden.
         F a0[KBNH][NT];
+        F pre[KBN1_USED];
+        // BF16 / FP8: the input-bit fragments are built once per tile of headers
+        constexpr bool kBitsOnce = PREC != TANG_FP32;
+        F bits[kBitsOnce ? KBN1_USED : 1][NT];
+        if constexpr (kBitsOnce) {
+#pragma unroll
+            for (int kb = 0; kb < KBN1_USED; ++kb)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) bits[kb][nt] = Bits<PREC>::get(hv[nt], kb, g);
+        }
+        if constexpr (!(LDSM & 1)) {
+#pragma unroll
+            for (int kb = 0; kb < KBN1_USED; ++kb) pre[kb] = ldf<false>(s1, r1, kb, lane, sbase);
+        }
 #pragma unroll
         for (int mt = 0; mt < MTH; ++mt) {
+            F cur[KBN1_USED];
+#pragma unroll
+            for (int kb = 0; kb < KBN1_USED; ++kb) {
+                if constexpr ((LDSM & 1) != 0) cur[kb] = ldf<true>(s1, r1, mt * KBN1 + kb, lane, sbase);
+                else cur[kb] = pre[kb];
+            }
+            if constexpr (!(LDSM & 1)) {
+                if (mt + 1 < MTH) {
+#pragma unroll
+                    for (int kb = 0; kb < KBN1_USED; ++kb)
+                        pre[kb] = ldf<false>(s1, r1, (mt + 1) * KBN1 + kb, lane, sbase);
+                }
+            }
             f4 acc[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[nt] = (f4){0, 0, 0, 0};
 #pragma unroll
             for (int kb = 0; kb < KBN1_USED; ++kb) {
-                const F A = ldf<(LDSM & 1) != 0>(s1, r1, mt * KBN1 + kb, lane, sbase);
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[nt] = mma(A, Bits<PREC>::get(hv[nt], kb, g), acc[nt]);
+                for (int nt = 0; nt < NT; ++nt) {
+                    if constexpr (kBitsOnce) acc[nt] = mma(cur[kb], bits[kb][nt], acc[nt]);
+                    else acc[nt] = mma(cur[kb], Bits<PREC>::get(hv[nt], kb, g), acc[nt]);
+                }
             }
             epi_hidden<PREC, NT, KBNH>(acc, mt, sb, a.deq[0], a.inv_a[1], g, a0);
             // keep the scheduler from hoisting every tile's fragment loads (register blow-up)
             __builtin_amdgcn_sched_barrier(0);
         }
-        // layer 2: H -> H
+        // layer 2: H -> H, TG output tiles per group: all MFMAs of the group are issued
+        // before its epilogues, so the matrix pipe has independent work while results land
         F a1[KBNH][NT];
 #pragma unroll
-        for (int mt = 0; mt < MTH; ++mt) {
-            f4 acc[NT];
+        for (int mt0 = 0; mt0 < MTH; mt0 += TG) {
+            f4 acc[TG][NT];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[nt] = (f4){0, 0, 0, 0};
+            for (int u = 0; u < TG; ++u)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[u][nt] = (f4){0, 0, 0, 0};
 #pragma unroll
             for (int kb = 0; kb < KBNH; ++kb) {
-                const F A = ldf<(LDSM & 2) != 0>(s2, r2, mt * KBNH + kb, lane, sbase);
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[nt] = mma(A, a0[kb][nt], acc[nt]);
+                for (int u = 0; u < TG; ++u) {
+                    const F A = ldf<(LDSM & 2) != 0>(s2, r2, (mt0 + u) * KBNH + kb, lane, sbase);
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[u][nt] = mma(A, a0[kb][nt], acc[u][nt]);
+                }
             }
-            epi_hidden<PREC, NT, KBNH>(acc, mt, sb + H, a.deq[1], a.inv_a[2], g, a1);
+#pragma unroll
+            for (int u = 0; u < TG; ++u)
+                epi_hidden<PREC, NT, KBNH>(acc[u], mt0 + u, sb + H, a.deq[1], a.inv_a[2], g, a1);
             __builtin_amdgcn_sched_barrier(0);
         }
         // layer 3: H -> C (two 16-row tiles)
@@ -333,7 +390,9 @@ uint8_t f32_to_e4m3(float f) {
 // Input column (of W[out][in]) that lane group g, element j of K block kb carries.
 int in_col(int prec, int layer, int kb, int g, int j) {
     if (prec == TANG_FP32) return layer == 0 ? 4 * kb + g : 16 * (kb / 4) + 4 * g + (kb % 4);
-    return layer == 0 ? 32 * kb + 8 * g + j : 16 * (2 * kb + (j >> 2)) + 4 * g + (j & 3);
+    if (prec == TANG_BF16)
+        return layer == 0 ? 32 * kb + 8 * g + j : 16 * (2 * kb + (j >> 2)) + 4 * g + (j & 3);
+    return layer == 0 ? 128 * kb + 32 * g + j : 16 * (8 * kb + (j >> 2)) + 4 * g + (j & 3);
 }
 
 }  // namespace
@@ -379,7 +438,8 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
     m.hidden = H;
     m.n_out = C;
     m.topk = (int)d->topk;
-    const int KB = p == TANG_FP32 ? 4 : 32, E = p == TANG_FP32 ? 1 : 8;
+    const int KB = p == TANG_FP32 ? 4 : p == TANG_BF16 ? 32 : 128;
+    const int E = p == TANG_FP32 ? 1 : p == TANG_BF16 ? 8 : 32;
     const int esz = p == TANG_FP32 ? 4 : p == TANG_BF16 ? 2 : 1;
     const int outs[3] = {H, H, C}, ins[3] = {104, H, H};
     const int outp[3] = {H, H, kOutPad}, inp[3] = {kInPad, H, H};
@@ -434,7 +494,7 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
 
 namespace {
 
-template <int PREC, int H, int NT, int LDSM>
+template <int PREC, int H, int NT, int LDSM, int WAVES = 8>
 hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, uint32_t* cand,
                     float* logits, uint8_t* cand8, hipStream_t s) {
     using F = typename FragT<PREC>::T;
@@ -443,7 +503,7 @@ hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, u
                      n3 = 2 * (H / KB) * 64;
     const size_t lds = ((LDSM & 1) ? n1 : 0) * sizeof(F) + ((LDSM & 2) ? n2 : 0) * sizeof(F) +
                        ((LDSM & 4) ? n3 : 0) * sizeof(F) + (2 * H + kOutPad) * sizeof(float);
-    auto kern = k_mlp<PREC, H, NT, LDSM>;
+    auto kern = k_mlp<PREC, H, NT, LDSM, WAVES>;
     static int attr_done = 0;  // per instantiation
     if (!attr_done) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -455,17 +515,17 @@ hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, u
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64 * kWaves, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64 * WAVES, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     const uint32_t tiles = (n + 16 * NT - 1) / (16 * NT);
-    const uint32_t want = (tiles + kWaves - 1) / kWaves;
+    const uint32_t want = (tiles + WAVES - 1) / WAVES;
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(want, (uint32_t)(cus * per_cu)));
     MlpArgs a;
     a.n_out = m.n_out;
     a.topk = m.topk;
     for (int l = 0; l < 3; ++l) { a.deq[l] = m.deq[l]; a.inv_a[l] = m.inv_a[l]; }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kWaves), lds, s,
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WAVES), lds, s,
                        reinterpret_cast<const uint4*>(d_hdr), n, (const F*)m.w[0], (const F*)m.w[1],
                        (const F*)m.w[2], m.bias, a, cand, logits, cand8);
     return hipGetLastError();
@@ -488,9 +548,9 @@ hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size
         if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 7>(m, h, k, c, lg, c8, s);
         else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0>(m, h, k, c, lg, c8, s);
         else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 7>(m, h, k, c, lg, c8, s);
-        else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 6>(m, h, k, c, lg, c8, s);
+        else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 6, 12>(m, h, k, c, lg, c8, s);
         else if (m.hidden == 128) e = launch_t<TANG_FP8, 128, 2, 7>(m, h, k, c, lg, c8, s);
-        else e = launch_t<TANG_FP8, 256, 2, 7>(m, h, k, c, lg, c8, s);
+        else e = launch_t<TANG_FP8, 256, 2, 7, 12>(m, h, k, c, lg, c8, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
