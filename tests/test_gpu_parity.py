@@ -143,15 +143,25 @@ def test_c1_1k_rules_all_weights_identical(ordering):
         T.tang_ruleset_destroy(rs)
 
 
+_C2 = {}
+
+
+def _c2_inputs():
+    """The 64k-rule configuration at full size: rules, 1,000,000 headers, oracle answers."""
+    if not _C2:
+        cfg = synth.CONFIGS["c2_64k"]
+        rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering="specificity", mix=cfg["mix"])
+        hdr = synth.make_packets(rules, cfg["n_pkts"], seed=cfg["seed"] + 1, frac_in=cfg["frac_in"])
+        _C2.update(rules=rules, hdr=hdr, want=orc.classify(rules, hdr))
+    return _C2["rules"], _C2["hdr"], _C2["want"]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_c2_64k_rules_mix(prec):
-    """65,536 rules with the 25% wildcard-heavy mix, 104 -> 256 -> 256 -> C; 200,000 of
-    the configuration's headers compared in full."""
+    """65,536 rules with the 25% wildcard-heavy mix, 104 -> 256 -> 256 -> C; all
+    1,000,000 headers of the configuration compared with the oracle."""
     torch_cuda()
-    cfg = synth.CONFIGS["c2_64k"]
-    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering="specificity", mix=cfg["mix"])
-    hdr = synth.make_packets(rules, 200_000, seed=cfg["seed"] + 1, frac_in=cfg["frac_in"])
-    want = orc.classify(rules, hdr)
+    rules, hdr, want = _c2_inputs()
     rs = T.tang_ruleset_create(0, rules)
     try:
         assert np.array_equal(classify_dev(rs, hdr), want)

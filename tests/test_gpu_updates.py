@@ -112,3 +112,36 @@ def test_growth_rehash_and_appended_tuple():
         assert np.array_equal(classify_dev(rs, pk), orc.classify(all_rules, pk, live=lm))
     finally:
         T.tang_ruleset_destroy(rs)
+
+
+def test_update_rounds_at_512k_sampled():
+    """The 512k-rule ruleset of the update workload: 3 rounds of 100 inserts + 100 deletes,
+    each followed by a 1M-header lookup from the live rules; a seeded 5,000-header sample
+    of every round equals the oracle's re-scan, and every answer contains its header."""
+    torch_cuda()
+    cfg = synth.CONFIGS["c4_512k_updates"]
+    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering="specificity")
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        C = T.tang_ruleset_num_tuples(rs)
+        Ws, bs = train.random_weights(C, 256, seed=3)
+        T.tang_model_load(rs, Ws, bs, "bf16")
+        all_rules = rules.copy()
+        live = set(int(i) for i in rules["id"])
+        for rd, (ins, dels) in enumerate(synth.make_update_stream(rules, 3, 100, seed=cfg["seed"] + 2,
+                                                                  prio_range=len(rules))):
+            T.tang_insert(rs, ins)
+            T.tang_delete(rs, dels)
+            all_rules = np.concatenate([all_rules, ins])
+            live |= set(int(i) for i in ins["id"])
+            live -= set(int(i) for i in dels)
+            lm = _live_mask(all_rules, live)
+            pk = synth.make_packets(all_rules[lm], cfg["n_pkts"], seed=rd, frac_in=cfg["frac_in"])
+            got = classify_dev(rs, pk)
+            samp = np.random.default_rng(rd).choice(len(pk), 5000, replace=False)
+            assert np.array_equal(got[samp], orc.classify(all_rules, pk[samp], live=lm)), rd
+            by_id = {int(r["id"]): k for k, r in enumerate(all_rules)}
+            for k in samp[:300]:
+                assert orc.rule_matches(all_rules[by_id[int(got[k])]], pk[k])
+    finally:
+        T.tang_ruleset_destroy(rs)
