@@ -139,16 +139,20 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                    filter_mask = s_misc[3];
     const uint32_t i = blockIdx.x * 256u + tid;
     uint32_t n_probe = 0, n_slots = 0, n_recs = 0, top1 = 0, fb = 0, nm = 0, active = 0;
+    uint32_t sip = 0, dip = 0, sp = 0, dp = 0, proto = 0, todo = 0, c0 = 0xFFu;
+    Best b{kDead, kDead, 0u, 0u};
     if (i < n) {
         active = 1;
         const uint4 h = hdr[i];
-        const uint32_t sip = h.x, dip = h.y, sp = h.z & 0xFFFFu, dp = h.z >> 16,
-                       proto = h.w & 0xFFu;
-        Best b{kDead, kDead, 0u, 0u};
+        sip = h.x;
+        dip = h.y;
+        sp = h.z & 0xFFFFu;
+        dp = h.z >> 16;
+        proto = h.w & 0xFFu;
         bool found = false;
-        const uint32_t cp = kcand > 0 ? out[i] : 0u;
-        uint32_t probed = 0, c0 = 0xFFu;
+        uint32_t probed = 0;
         if (kcand > 0) {
+            const uint32_t cp = out[i];
             for (int c = 0; c < kcand; ++c) {
                 const uint32_t t = (cp >> (8 * c)) & 0xFFu;
                 if (c == 0) c0 = t;
@@ -158,19 +162,29 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                 probe<STATS>(t, sip, dip, sp, dp, proto, s_t, slot_mask, filter_mask, filter, slots,
                              recs, b, n_probe, n_slots, n_recs);
             }
-            found = b.id != kDead || b.prio != kDead;
+            found = b.id != kDead;
         }
-        uint32_t todo = (found ? b.cmask : all_mask) & ~probed & all_mask;
+        todo = (found ? b.cmask : all_mask) & ~probed & all_mask;
         if (STATS) fb = found ? 0u : 1u;
-        for (uint32_t j = 0; j < ntup && todo; ++j) {
-            const uint32_t t = s_order[j];
-            if (!((todo >> t) & 1u)) continue;
-            if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) break;
+    }
+    // The remaining tuples in ascending best-key order. Every lane walks the same order,
+    // so the loop, the tuple index and its masks and best key are wave-uniform; a lane
+    // probes the tuples of its own list, and drops out once a tuple's best key cannot
+    // beat its answer (no later tuple can either).
+    for (uint32_t j = 0; j < ntup; ++j) {
+        const uint32_t t = __builtin_amdgcn_readfirstlane(s_order[j]);
+        const uint32_t bp = __builtin_amdgcn_readfirstlane(s_t[t].best_prio);
+        const uint32_t bid = __builtin_amdgcn_readfirstlane(s_t[t].best_id);
+        if (todo && !kless(bp, bid, b.prio, b.id)) todo = 0;
+        if (!__any(todo != 0)) break;
+        if ((todo >> t) & 1u) {
             todo &= ~(1u << t);
             probe<STATS>(t, sip, dip, sp, dp, proto, s_t, slot_mask, filter_mask, filter, slots, recs,
                          b, n_probe, n_slots, n_recs);
         }
-        found = b.id != kDead || b.prio != kDead;
+    }
+    if (active) {
+        const bool found = b.id != kDead;
         out[i] = found ? b.id : TANG_NO_MATCH;
         if (STATS) {
             top1 = (found && b.tuple == c0) ? 1u : 0u;

@@ -85,18 +85,24 @@ struct TupleTable {
     uint32_t filter_mask;             // filter bits - 1
 };
 
-// Key hash: MurmurHash3's 64-bit finaliser (fmix64, Appleby, public domain) over the
-// packed masked addresses, salted by the tuple index (golden-ratio multiple). The low 32
-// bits pick the slot, the high 32 bits pick the filter bit.
+// Key hash: two chained MurmurHash3 32-bit finalisers (fmix32, Appleby, public domain),
+// first over the masked SIP salted by the tuple index, then over that result xor the
+// masked DIP. Each stage is a bijection, so structured keys (prefixes whose only varying
+// bits are the top byte) do not collapse. The low half of the result picks the slot; the
+// high half, a further xorshift-multiply of it, picks the filter bit.
+__host__ __device__ inline uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
 __host__ __device__ inline uint64_t key_hash(uint32_t t, uint32_t ms, uint32_t md) {
-    uint64_t k = ((uint64_t)ms << 32) | md;
-    k ^= (uint64_t)(t + 1u) * 0x9E3779B97F4A7C15ull;
-    k ^= k >> 33;
-    k *= 0xFF51AFD7ED558CCDull;
-    k ^= k >> 33;
-    k *= 0xC4CEB9FE1A85EC53ull;
-    k ^= k >> 33;
-    return k;
+    const uint32_t h = fmix32(fmix32(ms + (t + 1u) * 0x9E3779B9u) ^ md);
+    uint32_t f = (h ^ (h >> 15)) * 0x2C1B3C6Du;
+    f ^= f >> 12;
+    return ((uint64_t)f << 32) | h;
 }
 __host__ __device__ inline uint32_t slot_of(uint64_t h) { return (uint32_t)h; }
 __host__ __device__ inline uint32_t filter_of(uint64_t h) { return (uint32_t)(h >> 32); }
