@@ -161,7 +161,8 @@ def main():
         assert np.array_equal(d_out.cpu().numpy().view(np.uint32), got_by_prec[prec])
         S = st["slots"] / n
         E = st["records"] / n
-        bytes_pkt = 13 + 4 + 4 + 16 * S + 32 * E
+        F = st["filter_checks"] / n
+        bytes_pkt = 13 + 4 + 4 + 4 * F + 16 * S + 32 * E
         per[prec] = dict(
             mpps=n * args.steps / wall / 1e6, ms_per_step=wall * 1e3 / args.steps,
             p50_ms=pct(step_ms, 50), p99_ms=pct(step_ms, 99),
@@ -171,9 +172,11 @@ def main():
             search_gbs=bytes_pkt * n / (k23 * 1e-3) / 1e9,
             probes_per_pkt=st["probes"] / n, slots_per_pkt=S, records_per_pkt=E,
             top1_hit_rate=st["top1_hits"] / n, fallback_rate=st["fallbacks"] / n,
-            search_bytes_per_pkt=bytes_pkt)
+            filter_checks_per_pkt=F, wave_steps=st["wave_steps"] / n,
+            wave_rounds=st["wave_rounds"] / n, search_bytes_per_pkt=bytes_pkt)
         log(f"[bench] {prec}: {per[prec]['mpps']:.0f} Mpps, mlp {k1:.3f} ms, search {k23:.3f} ms, "
-            f"probes/pkt {per[prec]['probes_per_pkt']:.2f}")
+            f"probes/pkt {per[prec]['probes_per_pkt']:.2f}, filter checks/pkt {F:.2f}, "
+            f"wave filter batches {per[prec]['wave_rounds']:.2f}, wave probe steps {per[prec]['wave_steps']:.2f}")
 
     probe_all = None
     if not args.skip_probe_all:

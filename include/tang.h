@@ -99,6 +99,9 @@ typedef struct tang_stats_s {
     uint64_t top1_hits;   /* answer lies in the first predicted tuple */
     uint64_t fallbacks;   /* nothing matched in the predicted tuples */
     uint64_t no_match;    /* packets with no matching rule at all */
+    uint64_t filter_checks;  /* bucket-filter bits read (one per tuple reached) */
+    uint64_t wave_steps;     /* per packet: most filter-passing tuples of a packet in its wave */
+    uint64_t wave_rounds;    /* per packet: filter-sweep batches (8 tuples) of its wave */
 } tang_stats_t;
 
 typedef struct tang_ruleset_s tang_ruleset_t;

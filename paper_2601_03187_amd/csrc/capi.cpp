@@ -194,7 +194,8 @@ static int run_search(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* 
         for (const StatsDev& p : part) {
             h.packets += p.packets; h.probes += p.probes; h.slots += p.slots;
             h.records += p.records; h.top1 += p.top1; h.fallbacks += p.fallbacks;
-            h.nomatch += p.nomatch;
+            h.nomatch += p.nomatch; h.filters += p.filters; h.steps += p.steps;
+            h.rounds += p.rounds;
         }
         stats->packets = h.packets;
         stats->probes = h.probes;
@@ -203,6 +204,9 @@ static int run_search(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* 
         stats->top1_hits = h.top1;
         stats->fallbacks = h.fallbacks;
         stats->no_match = h.nomatch;
+        stats->filter_checks = h.filters;
+        stats->wave_steps = h.steps;
+        stats->wave_rounds = h.rounds;
     }
     return TANG_OK;
 }

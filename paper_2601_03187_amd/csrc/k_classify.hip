@@ -4,12 +4,14 @@
 //      rules one by one in (priority, id) order -- the first match is the bucket's best;
 //   2. certify: if a rule matched, probe the tuples of its conflict mask (the only
 //      tuples that can hold a better matching rule); if nothing matched, probe every
-//      remaining tuple (the paper's post-verification search, Sec. 5.1.1);
-//   in both cases tuples are visited in ascending order of their best key and the
-//   search stops once a tuple's best key cannot beat the current answer.
+//      remaining tuple (the paper's post-verification search, Sec. 5.1.1); in both
+//      cases a tuple whose best (lowest) key cannot beat the current answer is skipped.
 // Before any slot walk, a bit of the bucket filter rules out a tuple that has no bucket
-// for the header's masked addresses (most certification probes); the bit is read only for
-// tuples the search actually reaches.
+// for the header's masked addresses. Certification first sweeps the filter for all of a
+// packet's remaining tuples, eight independent loads at a time, and then each lane walks
+// slots only for its own tuples whose bit is set. Both halves matter on a 64-lane wave:
+// one dependent L2 round trip per tuple would cost two dozen round trips back to back,
+// and a wave-uniform loop over tuples would pay for the union of all lanes' tuples.
 // Candidates come packed in the output word (one byte per candidate) from the MLP.
 #include "tang_internal.hpp"
 
@@ -52,9 +54,6 @@ __device__ __forceinline__ void scan_list(uint32_t off, uint32_t len, uint32_t s
     }
 }
 
-// Walks the open-addressing slots to key (tk, k0, k1); returns the slot, or an empty one.
-// The table is kept at most a third full, so an empty slot ends every walk; the step
-// bound only guards against a corrupted table.
 // Walks the open-addressing slots from hash h to key (tk, k0, k1); returns the slot, or
 // an empty one. The table is kept at most a third full, so an empty slot ends every
 // walk; the step bound only guards against a corrupted table.
@@ -72,20 +71,15 @@ __device__ __forceinline__ Slot find_slot(uint64_t h64, uint32_t tk, uint32_t k0
     return Slot{0, 0, kEmptyTL, 0};
 }
 
-// Searches tuple t for this header. One hash serves the filter bit (is there a bucket
-// for the header's masked key at all?) and the slot walk.
+// Searches tuple t for this header (its masked key and hash given): the slot walk to the
+// bucket, then the bucket's list, or for a split bucket the sub-lists the header selects.
 template <bool STATS>
-__device__ __forceinline__ void probe(uint32_t t, uint32_t sip, uint32_t dip, uint32_t sp,
-                                      uint32_t dp, uint32_t proto, const TupleDev* s_t,
-                                      uint32_t slot_mask, uint32_t filter_mask,
-                                      const uint32_t* __restrict__ filter,
-                                      const Slot* __restrict__ slots, const Rec* __restrict__ recs,
-                                      Best& b, uint32_t& n_probe, uint32_t& n_slots,
-                                      uint32_t& n_recs) {
-    const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
-    const uint64_t h = key_hash(t, ms, md);
-    const uint32_t bit = filter_of(h) & filter_mask;
-    if (!((filter[bit >> 5] >> (bit & 31u)) & 1u)) return;
+__device__ __forceinline__ void search_tuple(uint32_t t, uint64_t h, uint32_t ms, uint32_t md,
+                                             uint32_t sip, uint32_t dip, uint32_t sp, uint32_t dp,
+                                             uint32_t proto, uint32_t slot_mask,
+                                             const Slot* __restrict__ slots,
+                                             const Rec* __restrict__ recs, Best& b,
+                                             uint32_t& n_probe, uint32_t& n_slots, uint32_t& n_recs) {
     if (STATS) ++n_probe;
     const Slot s = find_slot<STATS>(h, t, ms, md, slot_mask, slots, n_slots);
     if (s.tl == kEmptyTL) return;
@@ -106,6 +100,37 @@ __device__ __forceinline__ void probe(uint32_t t, uint32_t sip, uint32_t dip, ui
     }
 }
 
+// Searches tuple t for this header after checking its filter bit (one hash serves both).
+template <bool STATS>
+__device__ __forceinline__ void probe(uint32_t t, uint32_t sip, uint32_t dip, uint32_t sp,
+                                      uint32_t dp, uint32_t proto, const TupleDev* s_t,
+                                      uint32_t slot_mask, uint32_t filter_mask,
+                                      const uint32_t* __restrict__ filter,
+                                      const Slot* __restrict__ slots, const Rec* __restrict__ recs,
+                                      Best& b, uint32_t& n_probe, uint32_t& n_slots,
+                                      uint32_t& n_recs, uint32_t& n_filter) {
+    const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
+    const uint64_t h = key_hash(t, ms, md);
+    const uint32_t bit = filter_of(h) & filter_mask;
+    if (STATS) ++n_filter;
+    if (!((filter[bit >> 5] >> (bit & 31u)) & 1u)) return;
+    search_tuple<STATS>(t, h, ms, md, sip, dip, sp, dp, proto, slot_mask, slots, recs, b, n_probe,
+                        n_slots, n_recs);
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, 64));
+    return v;
+}
+
+// OR of a 32-bit mask over the wave, as a wave-uniform value.
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -121,13 +146,15 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                                                   const TupleTable* __restrict__ ttg, int kcand,
                                                   StatsDev* __restrict__ st) {
     __shared__ TupleDev s_t[TANG_MAX_TUPLES];
-    __shared__ uint32_t s_order[TANG_MAX_TUPLES];
+    __shared__ uint2 s_rank[TANG_MAX_TUPLES];  // best keys in ascending order
+    __shared__ uint32_t s_prefix[TANG_MAX_TUPLES + 1];
     __shared__ uint32_t s_misc[4];
     const int tid = threadIdx.x;
     if (tid < TANG_MAX_TUPLES) {
         s_t[tid] = ttg->t[tid];
-        s_order[tid] = ttg->order[tid];
+        s_rank[tid] = make_uint2(ttg->rank_prio[tid], ttg->rank_id[tid]);
     }
+    if (tid <= TANG_MAX_TUPLES) s_prefix[tid] = ttg->prefix[tid];
     if (tid == 0) {
         s_misc[0] = ttg->n;
         s_misc[1] = ttg->all_mask;
@@ -139,6 +166,7 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                    filter_mask = s_misc[3];
     const uint32_t i = blockIdx.x * 256u + tid;
     uint32_t n_probe = 0, n_slots = 0, n_recs = 0, top1 = 0, fb = 0, nm = 0, active = 0;
+    uint32_t n_filter = 0, n_steps = 0, n_rounds = 0;
     uint32_t sip = 0, dip = 0, sp = 0, dp = 0, proto = 0, todo = 0, c0 = 0xFFu;
     Best b{kDead, kDead, 0u, 0u};
     if (i < n) {
@@ -160,29 +188,62 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                 probed |= 1u << t;
                 if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) continue;
                 probe<STATS>(t, sip, dip, sp, dp, proto, s_t, slot_mask, filter_mask, filter, slots,
-                             recs, b, n_probe, n_slots, n_recs);
+                             recs, b, n_probe, n_slots, n_recs, n_filter);
             }
             found = b.id != kDead;
         }
         todo = (found ? b.cmask : all_mask) & ~probed & all_mask;
         if (STATS) fb = found ? 0u : 1u;
     }
-    // The remaining tuples in ascending best-key order. Every lane walks the same order,
-    // so the loop, the tuple index and its masks and best key are wave-uniform; a lane
-    // probes the tuples of its own list, and drops out once a tuple's best key cannot
-    // beat its answer (no later tuple can either).
-    for (uint32_t j = 0; j < ntup; ++j) {
-        const uint32_t t = __builtin_amdgcn_readfirstlane(s_order[j]);
-        const uint32_t bp = __builtin_amdgcn_readfirstlane(s_t[t].best_prio);
-        const uint32_t bid = __builtin_amdgcn_readfirstlane(s_t[t].best_id);
-        if (todo && !kless(bp, bid, b.prio, b.id)) todo = 0;
-        if (!__any(todo != 0)) break;
-        if ((todo >> t) & 1u) {
-            todo &= ~(1u << t);
-            probe<STATS>(t, sip, dip, sp, dp, proto, s_t, slot_mask, filter_mask, filter, slots, recs,
-                         b, n_probe, n_slots, n_recs);
-        }
+    // Certification. First drop the tuples whose best key cannot beat the answer: the
+    // tuples in ascending best-key order form a prefix, found by a binary search.
+    if (todo) {
+        uint32_t k = 0;
+#pragma unroll
+        for (uint32_t step = 32; step > 0; step >>= 1)
+            if (k + step <= ntup && kless(s_rank[k + step - 1].x, s_rank[k + step - 1].y, b.prio, b.id))
+                k += step;
+        todo &= s_prefix[k];
     }
+    // Phase 1: the filter bits of every remaining tuple, eight tuples per batch with their
+    // loads issued back to back (batches no lane of the wave needs are skipped);
+    // `todo` keeps the tuples whose bit is set.
+    const uint32_t wave_todo = wave_or(todo);
+    uint32_t hits = 0;
+    for (uint32_t t0 = 0; t0 < ntup; t0 += 8) {
+        if (!((wave_todo >> t0) & 0xFFu)) continue;
+        if (STATS) ++n_rounds;
+        uint32_t w[8], pos[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t t = t0 + q;
+            w[q] = 0;
+            pos[q] = 0;
+            if ((todo >> t) & 1u) {  // t < ntup: todo holds only existing tuples
+                const uint32_t bit =
+                    filter_of(key_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask)) & filter_mask;
+                w[q] = filter[bit >> 5];
+                pos[q] = bit & 31u;
+                if (STATS) ++n_filter;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) hits |= ((w[q] >> pos[q]) & 1u) << (t0 + q);
+    }
+    // Phase 2: each lane searches its own passing tuples (so a wave takes as many steps as
+    // its busiest lane, not as the union of its lanes' tuples), skipping any whose best key
+    // can no longer beat the answer; the order does not matter for the result.
+    uint32_t steps = 0;
+    while (hits) {
+        const uint32_t t = __builtin_ctz(hits);
+        hits &= hits - 1u;
+        if (STATS) ++steps;
+        if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) continue;
+        const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
+        search_tuple<STATS>(t, key_hash(t, ms, md), ms, md, sip, dip, sp, dp, proto, slot_mask, slots,
+                            recs, b, n_probe, n_slots, n_recs);
+    }
+    if (STATS) n_steps = wave_max(steps);
     if (active) {
         const bool found = b.id != kDead;
         out[i] = found ? b.id : TANG_NO_MATCH;
@@ -194,15 +255,17 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
     if (STATS) {
         // wave sums -> block sums in LDS -> one set of atomics per block, spread over
         // kStatCopies counter copies (summed on the host) to avoid one hot address
-        __shared__ unsigned long long s_red[4][7];
-        unsigned long long v[7] = {active, n_probe, n_slots, n_recs, top1, fb, nm};
+        constexpr int NS = 10;
+        __shared__ unsigned long long s_red[4][NS];
+        unsigned long long v[NS] = {active, n_probe, n_slots, n_recs, top1, fb, nm, n_filter,
+                                    active ? n_steps : 0u, active ? n_rounds : 0u};
 #pragma unroll
-        for (int q = 0; q < 7; ++q) v[q] = wave_sum(v[q]);
+        for (int q = 0; q < NS; ++q) v[q] = wave_sum(v[q]);
         if ((tid & 63) == 0)
 #pragma unroll
-            for (int q = 0; q < 7; ++q) s_red[tid >> 6][q] = v[q];
+            for (int q = 0; q < NS; ++q) s_red[tid >> 6][q] = v[q];
         __syncthreads();
-        if (tid < 7) {
+        if (tid < NS) {
             const unsigned long long sum = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
             unsigned long long* dst = reinterpret_cast<unsigned long long*>(st + (blockIdx.x % kStatCopies));
             atomicAdd(dst + tid, sum);

@@ -30,6 +30,7 @@ typedef float fl2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 template <int PREC> struct FragT;
 template <> struct FragT<TANG_FP32> { using T = float; static constexpr int KB = 4; };
@@ -41,6 +42,7 @@ struct MlpArgs {
     int topk;
     float deq[3];
     float inv_a[3];
+    float hs[2];  // FP8 hidden layers: deq[l] * inv_a[l + 1] (product scale into next input)
 };
 
 namespace {
@@ -66,6 +68,14 @@ __device__ __forceinline__ f4 mma(u32x8 a, u32x8 b, f4 c) {
 
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((fl2){a, b}, bf16x2));
+}
+// ReLU of two packed BF16 values as one signed 16-bit max against 0: a BF16 with the
+// sign bit set is a negative int16, and non-negative BF16 order as their bit patterns.
+// RNE rounding never changes a value's sign, so ReLU after the rounding equals rounding
+// after ReLU.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t p) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p),
+                                                                  (s16x2){0, 0}));
 }
 // Four non-negative floats (already clamped to <= 448) -> four E4M3 bytes, RNE.
 __device__ __forceinline__ uint32_t pack_fp8(float a, float b, float c, float d) {
@@ -143,32 +153,36 @@ __device__ __forceinline__ F ldf(const F* lds, __amdgpu_buffer_rsrc_t r, uint32_
     else return bload(r, lane * (uint32_t)sizeof(F) + sbase, frag * 64u * (uint32_t)sizeof(F), (F*)nullptr);
 }
 
-// Bias + ReLU of one 16-row output tile and conversion into the next layer's B operand.
+// Accumulator start of one 16-row output tile: FP32 and BF16 layers fold the bias in as
+// the MFMA's C operand (the four rows this lane holds); FP8 products are scaled first, so
+// their bias is added in the epilogue.
+template <int PREC>
+__device__ __forceinline__ f4 acc_init(const float* sbias, int mt, int g) {
+    if constexpr (PREC == TANG_FP8) return (f4){0, 0, 0, 0};
+    else return *reinterpret_cast<const f4*>(sbias + 16 * mt + 4 * g);
+}
+
+// ReLU of one 16-row output tile and conversion into the next layer's B operand. FP8:
+// relu(acc * deq + b) * inv_next, clamped to 448, as one FMA with the folded scale
+// hs = deq * inv_next and the prescaled bias b * inv_next, and one median-of-three.
 template <int PREC, int NT, int KBN>
-__device__ __forceinline__ void epi_hidden(const f4 (&acc)[NT], int mt, const float* sbias, float deq,
-                                           float inv_next, int g,
-                                           typename FragT<PREC>::T (&dst)[KBN][NT]) {
-    float bv[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bv[r] = sbias[16 * mt + 4 * g + r];
+__device__ __forceinline__ void epi_hidden(const f4 (&acc)[NT], int mt, const float* sbias, float hs,
+                                           int g, typename FragT<PREC>::T (&dst)[KBN][NT]) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-        float v[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if constexpr (PREC == TANG_FP8) v[r] = fmaxf(acc[nt][r] * deq + bv[r], 0.0f);
-            else v[r] = fmaxf(acc[nt][r] + bv[r], 0.0f);
-        }
         if constexpr (PREC == TANG_FP32) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dst[4 * mt + r][nt] = v[r];
+            for (int r = 0; r < 4; ++r) dst[4 * mt + r][nt] = fmaxf(acc[nt][r], 0.0f);
         } else if constexpr (PREC == TANG_BF16) {
-            dst[mt >> 1][nt][2 * (mt & 1)] = pack_bf16(v[0], v[1]);
-            dst[mt >> 1][nt][2 * (mt & 1) + 1] = pack_bf16(v[2], v[3]);
+            dst[mt >> 1][nt][2 * (mt & 1)] = relu_bf16x2(pack_bf16(acc[nt][0], acc[nt][1]));
+            dst[mt >> 1][nt][2 * (mt & 1) + 1] = relu_bf16x2(pack_bf16(acc[nt][2], acc[nt][3]));
         } else {
-            // a 128-wide K block holds the rows of 8 consecutive output tiles
+            const f4 bv = *reinterpret_cast<const f4*>(sbias + 16 * mt + 4 * g);
+            float v[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = fminf(v[r] * inv_next, 448.0f);
+            for (int r = 0; r < 4; ++r)
+                v[r] = __builtin_amdgcn_fmed3f(__builtin_fmaf(acc[nt][r], hs, bv[r]), 0.0f, 448.0f);
+            // a 128-wide K block holds the rows of 8 consecutive output tiles
             dst[mt >> 3][nt][mt & 7] = pack_fp8(v[0], v[1], v[2], v[3]);
         }
     }
@@ -261,8 +275,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                 }
             }
             f4 acc[NT];
+            const f4 b0 = acc_init<PREC>(sb, mt, g);
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[nt] = (f4){0, 0, 0, 0};
+            for (int nt = 0; nt < NT; ++nt) acc[nt] = b0;
 #pragma unroll
             for (int kb = 0; kb < KBN1_USED; ++kb) {
 #pragma unroll
@@ -271,7 +286,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                     else acc[nt] = mma(cur[kb], Bits<PREC>::get(hv[nt], kb, g), acc[nt]);
                 }
             }
-            epi_hidden<PREC, NT, KBNH>(acc, mt, sb, a.deq[0], a.inv_a[1], g, a0);
+            epi_hidden<PREC, NT, KBNH>(acc, mt, sb, a.hs[0], g, a0);
             // keep the scheduler from hoisting every tile's fragment loads (register blow-up)
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -282,9 +297,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
         for (int mt0 = 0; mt0 < MTH; mt0 += TG) {
             f4 acc[TG][NT];
 #pragma unroll
-            for (int u = 0; u < TG; ++u)
+            for (int u = 0; u < TG; ++u) {
+                const f4 b0 = acc_init<PREC>(sb + H, mt0 + u, g);
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[u][nt] = (f4){0, 0, 0, 0};
+                for (int nt = 0; nt < NT; ++nt) acc[u][nt] = b0;
+            }
 #pragma unroll
             for (int kb = 0; kb < KBNH; ++kb) {
 #pragma unroll
@@ -296,7 +313,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
             }
 #pragma unroll
             for (int u = 0; u < TG; ++u)
-                epi_hidden<PREC, NT, KBNH>(acc[u], mt0 + u, sb + H, a.deq[1], a.inv_a[2], g, a1);
+                epi_hidden<PREC, NT, KBNH>(acc[u], mt0 + u, sb + H, a.hs[1], g, a1);
             __builtin_amdgcn_sched_barrier(0);
         }
         // layer 3: H -> C (two 16-row tiles)
@@ -478,8 +495,12 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
         m.wbytes[l] = buf.size();
         m.bytes += buf.size();
     }
+    // FP8 hidden biases are stored prescaled by the next layer's inverse activation scale
     std::vector<float> bias(2 * H + kOutPad, 0.0f);
-    for (int k = 0; k < H; ++k) { bias[k] = b[0][k]; bias[H + k] = b[1][k]; }
+    for (int k = 0; k < H; ++k) {
+        bias[k] = p == TANG_FP8 ? b[0][k] * m.inv_a[1] : b[0][k];
+        bias[H + k] = p == TANG_FP8 ? b[1][k] * m.inv_a[2] : b[1][k];
+    }
     for (int k = 0; k < C; ++k) bias[2 * H + k] = b[2][k];
     hipError_t e = hipMalloc(&m.bias, bias.size() * 4);
     if (e == hipSuccess) e = hipMemcpy(m.bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice);
@@ -525,6 +546,7 @@ hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, u
     a.n_out = m.n_out;
     a.topk = m.topk;
     for (int l = 0; l < 3; ++l) { a.deq[l] = m.deq[l]; a.inv_a[l] = m.inv_a[l]; }
+    for (int l = 0; l < 2; ++l) a.hs[l] = m.deq[l] * m.inv_a[l + 1];
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WAVES), lds, s,
                        reinterpret_cast<const uint4*>(d_hdr), n, (const F*)m.w[0], (const F*)m.w[1],
                        (const F*)m.w[2], m.bias, a, cand, logits, cand8);

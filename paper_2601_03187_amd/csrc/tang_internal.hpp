@@ -79,6 +79,8 @@ struct TupleDev {
 struct TupleTable {
     TupleDev t[TANG_MAX_TUPLES];
     uint8_t order[TANG_MAX_TUPLES];  // tuple indices by ascending best key
+    uint32_t rank_prio[TANG_MAX_TUPLES], rank_id[TANG_MAX_TUPLES];  // best keys in that order
+    uint32_t prefix[TANG_MAX_TUPLES + 1];  // prefix[k]: bits of the k tuples of lowest best key
     uint32_t n;                       // number of tuples
     uint32_t all_mask;                // bits of all tuples
     uint32_t slot_mask;               // slots - 1
@@ -114,7 +116,8 @@ __host__ __device__ inline uint32_t filter_of(uint64_t h) { return (uint32_t)(h 
 
 // Device-side counters for tang_stats_t (kStatCopies copies, summed on the host).
 struct StatsDev {
-    unsigned long long packets, probes, slots, records, top1, fallbacks, nomatch;
+    unsigned long long packets, probes, slots, records, top1, fallbacks, nomatch, filters, steps,
+        rounds;
 };
 constexpr int kStatCopies = 64;
 

@@ -162,7 +162,12 @@ TupleTable make_tuple_table(const tang_ruleset_t* rs) {
     std::iota(ord.begin(), ord.end(), 0u);
     std::stable_sort(ord.begin(), ord.end(),
                      [&](uint32_t a, uint32_t b) { return rs->tuple_best[a] < rs->tuple_best[b]; });
-    for (uint32_t i = 0; i < n; ++i) tt.order[i] = (uint8_t)ord[i];
+    for (uint32_t i = 0; i < n; ++i) {
+        tt.order[i] = (uint8_t)ord[i];
+        tt.rank_prio[i] = (uint32_t)(rs->tuple_best[ord[i]] >> 32);
+        tt.rank_id[i] = (uint32_t)rs->tuple_best[ord[i]];
+        tt.prefix[i + 1] = tt.prefix[i] | (1u << ord[i]);
+    }
     tt.n = n;
     tt.all_mask = n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u);
     tt.slot_mask = rs->slots.empty() ? 0 : (uint32_t)rs->slots.size() - 1;

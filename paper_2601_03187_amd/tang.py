@@ -40,7 +40,8 @@ class tang_mlp_desc_t(ctypes.Structure):
 
 class tang_stats_t(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in
-                ("packets", "probes", "slots", "records", "top1_hits", "fallbacks", "no_match")]
+                ("packets", "probes", "slots", "records", "top1_hits", "fallbacks", "no_match",
+                 "filter_checks", "wave_steps", "wave_rounds")]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

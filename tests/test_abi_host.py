@@ -35,7 +35,7 @@ def test_struct_sizes_match_header():
     assert synth.RULE_DTYPE.itemsize == 28 and synth.HDR_DTYPE.itemsize == 16
     import ctypes
     assert ctypes.sizeof(T.tang_mlp_desc_t) == 4 * 11
-    assert ctypes.sizeof(T.tang_stats_t) == 8 * 7
+    assert ctypes.sizeof(T.tang_stats_t) == 8 * 10
 
 
 def test_host_tuple_space_matches_table1(golden_tab_rules):
