@@ -155,6 +155,11 @@ int tang_model_unload(tang_ruleset_t* rs);
  * unless stats != NULL (then the counters are copied back and the call synchronises).
  * n = 0 is a no-op. Concurrent classify calls on any streams are allowed while no
  * update is in flight; order updates before classify through the streams.
+ * With a BF16 or FP8 model loaded, no stats and n >= 2^22, the batch is processed in
+ * chunks of 2^21 headers: each chunk's model runs on `stream` and its search on a stream
+ * the ruleset owns (created on first use), overlapping the next chunk's model; `stream`
+ * then waits for the last search, so completion is still observed through `stream`.
+ * Chunked calls on one ruleset share that stream, so their searches run one after another.
  */
 int tang_classify(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id,
                   size_t n, void* stream, tang_stats_t* stats);

@@ -52,6 +52,10 @@ static void free_device(tang_ruleset_t* rs) {
     if (rs->d_recs) hipFree(rs->d_recs);
     if (rs->d_tt) hipFree(rs->d_tt);
     if (rs->d_stats) hipFree(rs->d_stats);
+    for (hipEvent_t e : rs->pipe_events) hipEventDestroy(e);
+    rs->pipe_events.clear();
+    if (rs->pipe_stream) hipStreamDestroy(rs->pipe_stream);
+    rs->pipe_stream = nullptr;
     rs->d_slots = nullptr;
     rs->d_recs = nullptr;
     rs->d_tt = nullptr;
@@ -168,6 +172,8 @@ int tang_model_unload(tang_ruleset_t* rs) {
     return TANG_OK;
 }
 
+}  // extern "C"
+
 static int check_classify(const tang_ruleset_t* rs, const void* hdr, const void* out, size_t n) {
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
     if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset cannot classify");
@@ -211,17 +217,64 @@ static int run_search(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* 
     return TANG_OK;
 }
 
-int tang_classify(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id, size_t n,
-                  void* stream, tang_stats_t* stats) {
-    TANG_GUARD_BEGIN
+// Large batches with a model: chunk k's model runs on the caller's stream while chunk
+// k-1's search runs on the ruleset's own stream, so the MFMA-bound and the latency-bound
+// kernels overlap (and a chunk's headers are still cached when its search reads them).
+// The caller's stream waits for the last search, so the call completes in stream order.
+// If another thread is enqueueing a chunked call on the same ruleset, this call takes
+// the plain path instead of waiting for the lock.
+static int classify_chunked(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* out,
+                            size_t n, hipStream_t s, bool* done) {
+    *done = false;
+    std::unique_lock<std::mutex> lk(rs->pipe_mu, std::try_to_lock);
+    if (!lk.owns_lock()) return TANG_OK;
+    if (!rs->pipe_stream) TANG_HIP(hipStreamCreateWithFlags(&rs->pipe_stream, hipStreamNonBlocking));
+    const size_t K = (n + kPipeChunk - 1) / kPipeChunk;
+    while (rs->pipe_events.size() < K + 1) {
+        hipEvent_t e = nullptr;
+        TANG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        rs->pipe_events.push_back(e);
+    }
+    const int kcand = rs->model.topk;
+    for (size_t k = 0; k < K; ++k) {
+        const size_t base = k * kPipeChunk, m = std::min(kPipeChunk, n - base);
+        TANG_HIP(launch_mlp(rs, d_hdr + base, m, out + base, nullptr, nullptr, s));
+        TANG_HIP(hipEventRecord(rs->pipe_events[k], s));
+        TANG_HIP(hipStreamWaitEvent(rs->pipe_stream, rs->pipe_events[k], 0));
+        TANG_HIP(launch_classify(rs, d_hdr + base, out + base, m, kcand, rs->pipe_stream, false));
+    }
+    TANG_HIP(hipEventRecord(rs->pipe_events[K], rs->pipe_stream));
+    TANG_HIP(hipStreamWaitEvent(s, rs->pipe_events[K], 0));
+    *done = true;
+    return TANG_OK;
+}
+
+namespace tang {
+int classify_async(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id, size_t n,
+                   hipStream_t s, tang_stats_t* stats, bool allow_chunks) {
     int rc = check_classify(rs, d_hdr, d_rule_id, n);
     if (rc) return rc;
     if (stats) std::memset(stats, 0, sizeof *stats);
     if (n == 0) return TANG_OK;
-    hipStream_t s = (hipStream_t)stream;
     TANG_HIP(hipSetDevice(rs->device));
+    // (an FP32 model's MLP takes several times the search: nothing to overlap)
+    if (allow_chunks && rs->model.loaded && rs->model.prec != TANG_FP32 && !stats &&
+        n >= 2 * kPipeChunk) {
+        bool done = false;
+        rc = classify_chunked(rs, d_hdr, d_rule_id, n, s, &done);
+        if (rc || done) return rc;
+    }
     if (rs->model.loaded) TANG_HIP(launch_mlp(rs, d_hdr, n, d_rule_id, nullptr, nullptr, s));
     return run_search(rs, d_hdr, d_rule_id, n, s, stats);
+}
+}  // namespace tang
+
+extern "C" {
+
+int tang_classify(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id, size_t n,
+                  void* stream, tang_stats_t* stats) {
+    TANG_GUARD_BEGIN
+    return classify_async(rs, d_hdr, d_rule_id, n, (hipStream_t)stream, stats, true);
     TANG_GUARD_END
 }
 

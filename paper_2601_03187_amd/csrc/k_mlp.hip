@@ -1,7 +1,7 @@
 // Tuple predictor on MFMA: the plain MLP of Sec. 6.1 (FC -> ReLU -> FC -> ReLU -> FC,
 // 104 -> H -> H -> C) followed by argmax / top-k over the C tuple scores (Sec. 6.1,
 // Sec. 5.1.1), for FP32, BF16 and FP8 (OCP E4M3) operands with FP32 accumulation:
-// v_mfma_f32_16x16x4_f32, v_mfma_f32_16x16x32_bf16 and v_mfma_f32_16x16x32_fp8_fp8.
+// v_mfma_f32_16x16x4_f32, v_mfma_f32_16x16x32_bf16 and v_mfma_f32_16x16x128_f8f6f4.
 //
 // Orientation: every layer computes out^T = W * in^T with output neurons as MFMA rows
 // (the A operand, weights) and packets as MFMA columns (the B operand, activations).
@@ -30,6 +30,7 @@ typedef float fl2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 template <int PREC> struct FragT;
@@ -54,16 +55,13 @@ __device__ __forceinline__ f4 mma(u32x4 a, u32x4 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
-// FP8 (E4M3) x FP8 over a K = 128 block, as four K = 32 MFMAs on matching quarters of
-// the A and B fragments (the single-instruction K = 128 form,
-// v_mfma_scale_f32_16x16x128_f8f6f4, needs far more registers in this kernel).
+// FP8 (E4M3) x FP8 over a K = 128 block in one instruction (format codes 0 = E4M3 for
+// both operands). With both block-scale operands 0 the compiler emits the unscaled
+// v_mfma_f32_16x16x128_f8f6f4; the per-layer scales are applied in the epilogues.
 __device__ __forceinline__ f4 mma(u32x8 a, u32x8 b, f4 c) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(
-            __builtin_bit_cast(long, (u32x2){a[2 * q], a[2 * q + 1]}),
-            __builtin_bit_cast(long, (u32x2){b[2 * q], b[2 * q + 1]}), c, 0, 0, 0);
-    return c;
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(__builtin_bit_cast(i32x8, a),
+                                                            __builtin_bit_cast(i32x8, b), c, 0, 0,
+                                                            0, 0, 0, 0);
 }
 
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
@@ -130,7 +128,10 @@ template <> struct Bits<TANG_FP8> {
 
 // One lane's A fragment `frag` of a layer: from LDS, or from global memory through a
 // buffer descriptor (lane offset in one VGPR, fragment offset as a scalar; reads past the
-// layer's size return zero instead of faulting).
+// layer's size return zero instead of faulting). A fragment is stored as 64 consecutive
+// lane slots of at most 16 bytes; the 32-byte FP8 fragment as two such planes (bytes
+// 0-15 of every lane, then bytes 16-31), so that 128-bit LDS reads stay free of bank
+// conflicts.
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, float*) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
 }
@@ -140,17 +141,25 @@ __device__ __forceinline__ u32x2 bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uin
 __device__ __forceinline__ u32x4 bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, u32x4*) {
     return __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0);
 }
-__device__ __forceinline__ u32x8 bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, u32x8*) {
-    const u32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0);
-    const u32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(r, v + 16, s, 0);
-    return (u32x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-}
 
 template <bool IN_LDS, typename F>
 __device__ __forceinline__ F ldf(const F* lds, __amdgpu_buffer_rsrc_t r, uint32_t frag, uint32_t lane,
                                  uint32_t sbase) {
-    if constexpr (IN_LDS) return lds[frag * 64 + lane + sbase];  // sbase: opaque 0, see below
-    else return bload(r, lane * (uint32_t)sizeof(F) + sbase, frag * 64u * (uint32_t)sizeof(F), (F*)nullptr);
+    if constexpr (sizeof(F) == 32) {
+        u32x4 lo, hi;
+        if constexpr (IN_LDS) {
+            const u32x4* p = reinterpret_cast<const u32x4*>(lds);
+            lo = p[frag * 128 + lane + sbase];
+            hi = p[frag * 128 + 64 + lane + sbase];
+        } else {
+            lo = __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16u + sbase, frag * 2048u, 0);
+            hi = __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16u + sbase, frag * 2048u + 1024u, 0);
+        }
+        return (F){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    } else {
+        if constexpr (IN_LDS) return lds[frag * 64 + lane + sbase];  // sbase: opaque 0, see below
+        else return bload(r, lane * (uint32_t)sizeof(F) + sbase, frag * 64u * (uint32_t)sizeof(F), (F*)nullptr);
+    }
 }
 
 // Accumulator start of one 16-row output tile: FP32 and BF16 layers fold the bias in as
@@ -202,7 +211,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
     constexpr uint32_t n1 = MTH * KBN1 * 64, n2 = MTH * KBNH * 64, n3 = 2 * KBNH * 64;
     constexpr uint32_t nb = 2 * H + kOutPad;
     // output tiles per MFMA group in layer 2 (more when each tile is only 1-2 MFMAs)
-    constexpr int TG = PREC == TANG_FP8 ? 4 : PREC == TANG_BF16 ? 2 : 1;
+    constexpr int TG = PREC == TANG_FP8 ? 2 : PREC == TANG_BF16 ? 2 : 1;
 
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     F* s1 = reinterpret_cast<F*>(smem);
@@ -480,7 +489,11 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
                         const int row = 16 * mt + (lane & 15), g = lane >> 4;
                         const int c = in_col(p, l, kb, g, j);
                         const float w = (row < outs[l] && c < ins[l]) ? W[l][(size_t)row * ins[l] + c] : 0.0f;
-                        const size_t at = ((((size_t)mt * KBN + kb) * 64 + lane) * E + j) * esz;
+                        // FP8: two 16-byte planes per fragment (bytes j < 16, then j >= 16)
+                        const size_t frag = (size_t)mt * KBN + kb;
+                        const size_t at = p == TANG_FP8
+                                              ? ((frag * 2 + j / 16) * 64 + lane) * 16 + j % 16
+                                              : ((frag * 64 + lane) * E + j) * esz;
                         if (p == TANG_FP32) std::memcpy(&buf[at], &w, 4);
                         else if (p == TANG_BF16) {
                             const uint16_t q = f32_to_bf16(w);

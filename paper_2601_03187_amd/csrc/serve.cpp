@@ -99,7 +99,7 @@ int tang_server_s::graph_for(uint32_t tag, uint32_t cls, uint32_t si, hipGraphEx
     }
     StreamSlot& s = slots[si];
     TANG_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeRelaxed));
-    int rc = tang_classify(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr);
+    int rc = classify_async(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr, false);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s.stream, &graph);
     if (rc) {
@@ -136,7 +136,7 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, std::vector<std::shared_ptr
     TANG_HIP(hipMemcpyAsync(s.d_hdr, s.h_hdr, total * sizeof(tang_header_t), hipMemcpyHostToDevice,
                             s.stream));
     if (!warmed[tag]) {  // first use: eager call sets up kernel attributes before any capture
-        int rc = tang_classify(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr);
+        int rc = classify_async(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr, false);
         if (rc) return rc;
         TANG_HIP(hipStreamSynchronize(s.stream));
         warmed[tag] = 1;
@@ -147,7 +147,7 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, std::vector<std::shared_ptr
         if (rc) return rc;
         TANG_HIP(hipGraphLaunch(exec, s.stream));
     } else {
-        int rc = tang_classify(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr);
+        int rc = classify_async(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr, false);
         if (rc) return rc;
     }
     TANG_HIP(hipMemcpyAsync(s.h_out, s.d_out, total * sizeof(uint32_t), hipMemcpyDeviceToHost,

@@ -199,6 +199,11 @@ struct tang_ruleset_s {
     hipStream_t upd_stream = nullptr;
     tang::ModelDev model;
     std::mutex stats_mu;
+    // Chunked classify: the searches of a large batch run on this stream (created on first
+    // use, default priority), each after its chunk's model on the caller's stream.
+    std::mutex pipe_mu;
+    hipStream_t pipe_stream = nullptr;
+    std::vector<hipEvent_t> pipe_events;
     uint64_t version = 0;   // bumped by every change that captured launches depend on
 
     size_t device_bytes() const;
@@ -237,6 +242,13 @@ hipError_t launch_move_records(Rec* d_recs, const Rec* d_src_recs, const uint32_
                                const uint32_t* d_dst, uint32_t n, Rec* d_stage, hipStream_t s);
 hipError_t launch_scatter_slots(Slot* d_slots, const uint32_t* d_idx, const Slot* d_val,
                                 uint32_t n, hipStream_t s);
+// Batches of at least two chunks of this many headers, with a BF16 or FP8 model and no
+// stats, are classified chunk by chunk with the model and the search on two streams.
+constexpr size_t kPipeChunk = (size_t)1 << 21;
+// tang_classify's body; allow_chunks = false keeps every launch on stream s (for callers
+// that capture the launches into a graph).
+int classify_async(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id, size_t n,
+                   hipStream_t s, tang_stats_t* stats, bool allow_chunks);
 hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
                       uint32_t* d_cand_packed, float* d_logits, uint8_t* d_cand8,
                       hipStream_t s);

@@ -9,7 +9,7 @@ from oracle import oracle as orc
 from paper_2601_03187_amd import synth, train
 from paper_2601_03187_amd import tang as T
 from tests import _golden
-from tests._gpu import classify_dev, keys_of, torch_cuda
+from tests._gpu import classify_dev, keys_of, to_dev, torch_cuda
 
 pytestmark = pytest.mark.gpu
 NO = T.TANG_NO_MATCH
@@ -171,6 +171,35 @@ def test_c2_64k_rules_mix(prec):
         got, st = classify_dev(rs, hdr, stats=True)
         assert np.array_equal(got, want)
         assert st["packets"] == len(hdr) and st["probes"] <= 25 * len(hdr)
+    finally:
+        T.tang_ruleset_destroy(rs)
+
+
+def test_chunked_two_stream_classify_equals_oracle():
+    """A batch of at least two 2^21-header chunks with a model is classified chunk by
+    chunk, the searches on the ruleset's own stream: the 1,000,000 headers of the 64k
+    configuration tiled to 4,194,304 + 777 (three chunks, the last ragged), every answer
+    compared with the oracle's, on a side stream, twice in a row, for top-1 and top-2."""
+    torch = torch_cuda()
+    rules, hdr, want = _c2_inputs()
+    reps = (2 * (1 << 21) + 777 + len(hdr) - 1) // len(hdr)
+    big = np.concatenate([hdr] * reps)[: 2 * (1 << 21) + 777]
+    big_want = np.concatenate([want] * reps)[: len(big)]
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        C = T.tang_ruleset_num_tuples(rs)
+        Ws, bs = train.random_weights(C, 256, seed=9)
+        d_hdr = to_dev(big)
+        d_out = torch.empty(len(big), dtype=torch.int32, device="cuda")
+        side = torch.cuda.Stream()
+        for topk in (1, 2):
+            T.tang_model_load(rs, Ws, bs, "bf16", topk=topk)
+            for _ in range(2):
+                d_out.fill_(-7)
+                torch.cuda.synchronize()
+                T.tang_classify(rs, d_hdr, d_out, len(big), side)
+                side.synchronize()
+                assert np.array_equal(d_out.cpu().numpy().view(np.uint32), big_want), topk
     finally:
         T.tang_ruleset_destroy(rs)
 
