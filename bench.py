@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-literal", action="store_true")
     ap.add_argument("--skip-probe-all", action="store_true")
+    ap.add_argument("--skip-configs", action="store_true",
+                    help="skip the 1k / 64k configurations and the 80%%-rule-sampled 512k run")
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
                     help="c3: 512k rules / 16M headers (the headline line); c4: the update "
                          "stream on the 512k ruleset; c5: the serving loop over three rulesets")
@@ -236,6 +238,11 @@ def main():
         del ld
         log(f"[bench] literal ordering: {lit['mpps']:.0f} Mpps")
 
+    configs = None
+    if not args.skip_configs:
+        T.tang_model_load(rs, Ws, bs, base, topk=1, act_scales=sc if base == "fp8" else None)
+        configs = other_configs(args, rules, rs, d_hdr, base)
+
     # oracle: CPU baseline on a bounded seeded sample, and the bit-exact check
     cpu = None
     exact = None
@@ -246,9 +253,14 @@ def main():
         t0 = time.perf_counter()
         want = orc.classify(rules, hdr[samp], threads=threads)
         el = time.perf_counter() - t0
+        s1 = samp[:20_000]
+        t0 = time.perf_counter()
+        orc.classify(rules, hdr[s1], threads=1)
+        el1 = time.perf_counter() - t0
         cpu = {"value": len(samp) / el / 1e6, "unit": "Mpps", "cores": threads, "kind": "oracle",
                "sample": f"{len(samp)} of the {n} headers (seeded), same 524,288-rule ruleset; "
-                         f"linear scan in (priority, id) order, {el:.1f}s wall"}
+                         f"linear scan in (priority, id) order, {el:.1f}s wall",
+               "one_thread_mpps": len(s1) / el1 / 1e6, "cpu_model": cpu_model()}
         mism = {p: int((g[samp] != want).sum()) for p, g in got_by_prec.items()}
         exact = {"sample": int(len(samp)), "mismatches": mism,
                  "bit_exact": all(v == 0 for v in mism.values())}
@@ -287,7 +299,7 @@ def main():
         "bit_exact": exact,
         "roofline": roof, "kernels": other,
         "per_precision": per, "candidate_change_vs_fp32": cand_change,
-        "literal_ordering": lit, "no_model_probe_all": probe_all,
+        "literal_ordering": lit, "no_model_probe_all": probe_all, "other_configs": configs,
         "build_s": build_s, "train_top1": acc,
         "cpu_baseline": cpu,
         "paper_context": "TaNG reports 10.98 Mpps average at 512k rules (12 ClassBench-ng rulesets, "
@@ -296,6 +308,94 @@ def main():
     print(json.dumps(line), flush=True)
     T.tang_ruleset_destroy(rs)
 
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_classify(T, rs, d_hdr, d_out, n, reps):
+    """Mean ms of tang_classify over `reps` launches after 3 warm-ups (HIP events)."""
+    import torch
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        T.tang_classify(rs, d_hdr, d_out, n, s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        T.tang_classify(rs, d_hdr, d_out, n, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def other_configs(args, rules3, rs3, d_hdr3, prec3):
+    """The 1k-rule (FP32, 104-128-128-C) and 64k-rule wildcard-mix (FP32 vs BF16) workloads,
+    and the 512k ruleset with 80% rule-sampled headers: Mpps, probes per header, answers
+    against the oracle (all of them at 1k, a seeded sample otherwise), and at 64k the
+    share of headers whose BF16 candidate differs from the FP32 one."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as orc
+    from paper_2601_03187_amd import synth, train
+    from paper_2601_03187_amd import tang as T
+
+    res = {}
+    for name, precs in (("c1_1k", ("fp32",)), ("c2_64k", ("fp32", "bf16"))):
+        cfg = synth.CONFIGS[name]
+        rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering="specificity", mix=cfg["mix"])
+        hdr = synth.make_packets(rules, cfg["n_pkts"], seed=cfg["seed"] + 1, frac_in=cfg["frac_in"])
+        n = len(hdr)
+        rs = T.tang_ruleset_create(0, rules)
+        Ws, bs, sc, acc = train.fit(rs, rules, hdr[:200_000], cfg["hidden"], steps=500, seed=1,
+                                    device="cuda")
+        d_hdr = torch.from_numpy(hdr.view(np.uint8).reshape(-1)).cuda()
+        d_out = torch.empty(n, dtype=torch.int32, device="cuda")
+        samp = np.arange(n) if n <= 10_000 else np.sort(np.random.default_rng(11).choice(n, 100_000, replace=False))
+        want = orc.classify(rules, hdr[samp])
+        out = {"rules": len(rules), "headers": n, "hidden": cfg["hidden"], "train_top1": acc}
+        cands = {}
+        for p in precs:
+            T.tang_model_load(rs, Ws, bs, p, topk=1)
+            st = T.tang_classify(rs, d_hdr, d_out, n, torch.cuda.current_stream(), want_stats=True)
+            got = d_out.cpu().numpy().view(np.uint32)
+            ms = time_classify(T, rs, d_hdr, d_out, n, 50 if n <= 10_000 else 20)
+            T.tang_predict(rs, d_hdr, d_out, n, torch.cuda.current_stream())
+            cands[p] = d_out.cpu().numpy().view(np.uint32) & 0xFF
+            out[p] = {"mpps": n / ms / 1e3, "ms_per_batch": ms, "probes_per_pkt": st["probes"] / n,
+                      "records_per_pkt": st["records"] / n, "fallback_rate": st["fallbacks"] / n,
+                      "oracle_checked": int(len(samp)), "mismatches": int((got[samp] != want).sum())}
+        if "bf16" in cands:
+            out["candidate_change_bf16_vs_fp32"] = float(np.mean(cands["bf16"] != cands["fp32"]))
+        res[name] = out
+        T.tang_ruleset_destroy(rs)
+        del d_hdr, d_out
+        log(f"[bench] {name}: " + ", ".join(f"{p} {out[p]['mpps']:.0f} Mpps ({out[p]['mismatches']} "
+                                             f"mismatches of {out[p]['oracle_checked']})" for p in precs))
+    cfg = synth.CONFIGS["c3_512k"]
+    n = cfg["n_pkts"]
+    hdr = synth.make_packets(rules3, n, seed=cfg["seed"] + 7, frac_in=0.8, zipf_s=cfg["zipf"])
+    d_hdr = torch.from_numpy(hdr.view(np.uint8).reshape(-1)).cuda()
+    d_out = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = T.tang_classify(rs3, d_hdr, d_out, n, torch.cuda.current_stream(), want_stats=True)
+    got = d_out.cpu().numpy().view(np.uint32)
+    samp = np.sort(np.random.default_rng(12).choice(n, 20_000, replace=False))
+    want = orc.classify(rules3, hdr[samp])
+    ms = time_classify(T, rs3, d_hdr, d_out, n, args.steps)
+    res["c3_512k_80pct_inside"] = {"precision": prec3, "mpps": n / ms / 1e3, "ms_per_batch": ms,
+                                   "probes_per_pkt": st["probes"] / n, "no_match_rate": st["no_match"] / n,
+                                   "oracle_checked": int(len(samp)),
+                                   "mismatches": int((got[samp] != want).sum())}
+    log(f"[bench] c3 with 80% rule-sampled headers: {res['c3_512k_80pct_inside']['mpps']:.0f} Mpps")
+    return res
 
 
 def bench_updates(args):
