@@ -579,13 +579,15 @@ hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size
         float* lg = d_logits ? d_logits + base * (size_t)m.n_out : nullptr;
         uint8_t* c8 = d_cand8 ? d_cand8 + base * (size_t)m.topk : nullptr;
         hipError_t e;
-        // LDSM: which layers' fragments sit in LDS (bit l = layer l) -- 160 KB per CU
+        // LDSM: which layers' fragments sit in LDS (bit l = layer l) -- 160 KB per CU.
+        // H = 256 runs 8 waves per CU (2 per SIMD): fewer than the register file would
+        // hold, so that a chunked classify's search waves fit beside them.
         if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 7>(m, h, k, c, lg, c8, s);
         else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0>(m, h, k, c, lg, c8, s);
         else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 7>(m, h, k, c, lg, c8, s);
-        else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 6, 12>(m, h, k, c, lg, c8, s);
+        else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 6, 8>(m, h, k, c, lg, c8, s);
         else if (m.hidden == 128) e = launch_t<TANG_FP8, 128, 2, 7>(m, h, k, c, lg, c8, s);
-        else e = launch_t<TANG_FP8, 256, 2, 7, 12>(m, h, k, c, lg, c8, s);
+        else e = launch_t<TANG_FP8, 256, 2, 7, 8>(m, h, k, c, lg, c8, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
