@@ -22,6 +22,11 @@ Contents, each written from the passage it cites:
                              BF16 / FP8 quantisation steps emulated on the inputs of
                              each layer; ``topk`` picks predicted tuples (argmax of
                              Sec. 6.1, ties to the lower index).
+* ``segments`` / ``resnet_forward`` -- the paper's own model input and network
+                             (Sec. 6.2 input format, Sec. 6.1 with residual blocks,
+                             Eq. 1, sizes of Sec. 7.1): seven 16-bit header chunks as
+                             floats, FC -> ReLU, residual blocks, FC; float64 with the
+                             BF16 rounding steps emulated.
 * ``tuples_first_appearance`` / ``rule_tuples`` -- tuple space (Sec. 4.3): rules
                              grouped by their (SIP length, DIP length) signature,
                              numbered by first appearance in priority order (Table 1).
@@ -262,6 +267,55 @@ def mlp_abs_forward(x: np.ndarray, Ws, bs) -> list:
         m = a @ np.abs(np.asarray(W, np.float64)).T + np.abs(np.asarray(b, np.float64))
         mags.append(m)
         a = m
+    return mags
+
+
+def segments(pkts: np.ndarray) -> np.ndarray:
+    """The model input of Sec. 6.2: the header cut into 16-bit chunks -- SIP high, SIP low,
+    DIP high, DIP low, SP, DP, PROTO -- each turned into a float. The scale is unstated;
+    read here as the chunk value divided by 65535, so every input lies in [0, 1]."""
+    sip = pkts["sip"].astype(np.int64)
+    dip = pkts["dip"].astype(np.int64)
+    cols = [sip >> 16, sip & 0xFFFF, dip >> 16, dip & 0xFFFF,
+            pkts["sp"].astype(np.int64), pkts["dp"].astype(np.int64), pkts["proto"].astype(np.int64)]
+    return np.stack(cols, axis=1).astype(np.float64) / 65535.0
+
+
+def resnet_forward(s: np.ndarray, Ws, bs, precision: str = "bf16") -> np.ndarray:
+    """Logits (float64) of the network of Sec. 6.1 with residual blocks: an input FC layer
+    with ReLU, then blocks B(x) = relu(relu(x w1 + b1) w2 + b2 + x) (Eq. 1, its unbalanced
+    parentheses read as the usual residual block with the ReLU after the sum), then an
+    output FC layer without activation. Ws = [W_in, W_11, W_12, ..., W_k1, W_k2, W_out]
+    in nn.Linear layout [out][in], bs likewise. The input layer (seven inputs) is computed
+    unrounded; with precision "bf16" every later layer's weights and inputs are rounded to
+    bfloat16 (the residual term x is the rounded block input), biases stay unrounded."""
+    if precision == "fp32":
+        rnd = lambda a: a  # noqa: E731
+    elif precision == "bf16":
+        rnd = bf16_round
+    else:
+        raise ValueError(precision)
+    f64 = lambda a: np.asarray(a, dtype=np.float64)  # noqa: E731
+    a = np.maximum(f64(s) @ f64(Ws[0]).T + f64(bs[0]), 0.0)
+    n_blocks = (len(Ws) - 2) // 2
+    for k in range(n_blocks):
+        W1, b1, W2, b2 = Ws[1 + 2 * k], bs[1 + 2 * k], Ws[2 + 2 * k], bs[2 + 2 * k]
+        x = rnd(a)
+        h = np.maximum(x @ rnd(f64(W1)).T + f64(b1), 0.0)
+        a = np.maximum(rnd(h) @ rnd(f64(W2)).T + f64(b2) + x, 0.0)
+    return rnd(a) @ rnd(f64(Ws[-1])).T + f64(bs[-1])
+
+
+def resnet_abs_forward(s: np.ndarray, Ws, bs) -> list:
+    """Magnitudes |W||a| + |b| (+ the residual's |x|) after every layer, for error bounds."""
+    f64 = lambda a: np.abs(np.asarray(a, dtype=np.float64))  # noqa: E731
+    a = f64(s) @ f64(Ws[0]).T + f64(bs[0])
+    mags = [a]
+    for k in range((len(Ws) - 2) // 2):
+        h = a @ f64(Ws[1 + 2 * k]).T + f64(bs[1 + 2 * k])
+        a = h @ f64(Ws[2 + 2 * k]).T + f64(bs[2 + 2 * k]) + a
+        mags += [h, a]
+    mags.append(a @ f64(Ws[-1]).T + f64(bs[-1]))
     return mags
 
 
