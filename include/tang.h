@@ -149,6 +149,31 @@ int tang_model_load(tang_ruleset_t* rs, const tang_mlp_desc_t* desc, const float
 int tang_model_unload(tang_ruleset_t* rs);
 
 /*
+ * The paper's own predictor (Sec. 6.1 with residual blocks, Eq. 1; sizes of Sec. 7.1) on
+ * its model input (Sec. 6.2): the header cut into seven 16-bit chunks (SIP high, SIP low,
+ * DIP high, DIP low, SP, DP, PROTO), each divided by 65535; FC(7 -> width) + ReLU; then
+ * n_blocks blocks x <- relu(relu(x w1 + b1) w2 + b2 + x); then FC(width -> C); top-k.
+ * W / b: 2 + 2 n_blocks host pointers in nn.Linear layout [out][in]: W[0] width x 7,
+ * W[1 + 2k] and W[2 + 2k] (block k's two layers) width x width, W[last] C x width.
+ * Precision: BF16 only (the input layer is computed in FP32; every later layer's weights
+ * and inputs are rounded to bfloat16, nearest-even; FP32 accumulation and biases).
+ * Deep copy; replaces any loaded model. The library also allocates a 192 MB activation
+ * workspace (three buffers of 65,536 headers x 512 BF16); calls that use this model on
+ * one ruleset are ordered on the device through an event, whatever their streams.
+ * Errors: EINVAL (width != 512, n_blocks outside 1..16, n_out != C, topk outside
+ * 1..min(4, C), precision not BF16, NULL pointers), ENOMEM, EDEVICE.
+ */
+typedef struct tang_resnet_desc_s {
+    uint32_t width;     /* neurons per FC layer: 512 */
+    uint32_t n_blocks;  /* residual blocks (the paper uses 6) */
+    uint32_t n_out;     /* C: the number of tuples */
+    uint32_t topk;      /* candidates per header, 1..min(4, C) */
+} tang_resnet_desc_t;
+int tang_model_load_resnet(tang_ruleset_t* rs, const tang_resnet_desc_t* desc,
+                           const float* const* W, const float* const* b,
+                           tang_precision_t precision);
+
+/*
  * Classify n headers: d_rule_id[i] = id of the highest-priority live rule matching
  * d_hdr[i], or TANG_NO_MATCH. d_hdr, d_rule_id: device pointers on the ruleset's GPU,
  * caller-owned, valid until the stream has passed this work. Asynchronous on `stream`

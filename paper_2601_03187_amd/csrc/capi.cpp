@@ -161,6 +161,17 @@ int tang_model_load(tang_ruleset_t* rs, const tang_mlp_desc_t* desc, const float
     TANG_GUARD_END
 }
 
+int tang_model_load_resnet(tang_ruleset_t* rs, const tang_resnet_desc_t* desc, const float* const* W,
+                           const float* const* b, tang_precision_t precision) {
+    TANG_GUARD_BEGIN
+    if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset cannot hold a model");
+    TANG_HIP(hipSetDevice(rs->device));
+    TANG_HIP(hipDeviceSynchronize());  // no classify may still read the old weights
+    return resnet_prepare(rs, desc, W, b, precision);
+    TANG_GUARD_END
+}
+
 int tang_model_unload(tang_ruleset_t* rs) {
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
     if (rs->device != TANG_HOST_ONLY) {

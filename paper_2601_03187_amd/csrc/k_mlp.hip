@@ -430,6 +430,16 @@ void model_free(ModelDev& m) {
     }
     if (m.bias) hipFree(m.bias);
     m.bias = nullptr;
+    if (m.rin) hipFree(m.rin);
+    if (m.rw) hipFree(m.rw);
+    if (m.ws) hipFree(m.ws);
+    if (m.ws_done) hipEventDestroy(m.ws_done);
+    m.rin = nullptr;
+    m.rw = nullptr;
+    m.ws = nullptr;
+    m.ws_done = nullptr;
+    m.ws_used = false;
+    m.kind = 0;
     m.loaded = 0;
     m.bytes = 0;
 }
@@ -571,6 +581,7 @@ hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, u
 hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
                       uint32_t* d_cand_packed, float* d_logits, uint8_t* d_cand8, hipStream_t s) {
     const ModelDev& m = rs->model;
+    if (m.kind == 1) return launch_resnet(rs, d_hdr, n, d_cand_packed, d_logits, d_cand8, s);
     const size_t chunk = (size_t)1 << 30;
     for (size_t base = 0; base < n; base += chunk) {
         const uint32_t k = (uint32_t)std::min(chunk, n - base);

@@ -1,0 +1,352 @@
+// The paper's own tuple predictor: the network of Sec. 6.1 with residual blocks (Eq. 1)
+// at the size of Sec. 7.1, on the model input of Sec. 6.2:
+//   seven 16-bit header chunks / 65535 -> FC(7 -> 512) + ReLU
+//   -> n blocks  x <- relu(relu(x w1 + b1) w2 + b2 + x)
+//   -> FC(512 -> C) -> top-k (ties to the lower tuple index).
+// About 3.2 M multiply-adds per header with 6.3 MB of BF16 weights: the weights cannot
+// stay in LDS as the small predictor's do, so every 512 x 512 layer is one MFMA GEMM over
+// a chunk of headers. Activations are BF16 rows of 512 per header in a library-owned
+// workspace of three chunk buffers (block input / residual, block middle, block output),
+// small enough to stay in the Infinity Cache; each layer's 512 KB of weights is read from
+// L2 by every workgroup. The input layer (seven inputs) runs in FP32 on the vector ALUs.
+//
+// MFMA orientation as in the small predictor: weights are the A operand (rows = output
+// neurons), headers the B operand (columns). Both operands are read straight from their
+// row-major rows: lane group g supplies elements 8g..8g+7 of every 32-wide K block on both
+// sides, so the products pair up whatever the instruction's internal K order is. A 16x16
+// result leaves lane (g, c) holding neurons 4g..4g+3 of header c: four consecutive BF16 of
+// that header's output row, stored as one 8-byte write.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "tang_internal.hpp"
+
+namespace tang {
+namespace {
+
+constexpr int kW = 512;               // neurons per layer
+constexpr uint32_t kChunk = 65536;    // headers per workspace pass (3 x 64 MB)
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f4 mma(u32x4 a, u32x4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((fl2){a, b}, bf16x2));
+}
+// ReLU of two packed BF16 as a signed 16-bit max against 0 (RNE keeps signs, so this
+// equals rounding after ReLU).
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t p) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p),
+                                                                  (s16x2){0, 0}));
+}
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes, 0x00020000);
+}
+
+// Input layer: one wave per header, lane l computes neurons 8l..8l+7 (FP32 FMAs over the
+// seven chunks, ReLU, BF16) and writes them as one 16-byte store.
+__global__ __launch_bounds__(256) void k_res_input(const uint4* __restrict__ hdr, uint32_t m,
+                                                   const float* __restrict__ win,
+                                                   const float* __restrict__ bin,
+                                                   u32x4* __restrict__ x) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    float w[8][7], b[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t n = 8u * lane + j;
+        b[j] = bin[n];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) w[j][q] = win[n * 8 + q];
+    }
+    for (uint32_t p = wave; p < m; p += nwaves) {
+        const uint4 h = hdr[p];
+        const float s[7] = {(float)(h.x >> 16) / 65535.0f, (float)(h.x & 0xFFFFu) / 65535.0f,
+                            (float)(h.y >> 16) / 65535.0f, (float)(h.y & 0xFFFFu) / 65535.0f,
+                            (float)(h.z & 0xFFFFu) / 65535.0f, (float)(h.z >> 16) / 65535.0f,
+                            (float)(h.w & 0xFFu) / 65535.0f};
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float a = b[j];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) a = __builtin_fmaf(w[j][q], s[q], a);
+            v[j] = a;
+        }
+        x[(size_t)p * (kW / 8) + lane] =
+            (u32x4){relu_bf16x2(pack_bf16(v[0], v[1])), relu_bf16x2(pack_bf16(v[2], v[3])),
+                    relu_bf16x2(pack_bf16(v[4], v[5])), relu_bf16x2(pack_bf16(v[6], v[7]))};
+    }
+}
+
+// One 512 x 512 layer: out = relu(W in + b [+ res]) over m header rows, BF16 in and out,
+// FP32 accumulation with the bias as the accumulator's start. Workgroup: 8 waves and 128
+// headers; wave w computes neurons 64w..64w+63 (4 row tiles) for all 128 headers (8 column
+// tiles). K advances 32 at a time with the next step's fragments loaded before the
+// current step's 32 MFMAs. Rows past m read as zero (buffer range check) and are not
+// written.
+template <bool RES>
+__global__ __launch_bounds__(512) void k_res_dense(const uint16_t* __restrict__ in,
+                                                   const uint16_t* __restrict__ w,
+                                                   const float* __restrict__ bias,
+                                                   const uint16_t* __restrict__ res,
+                                                   uint16_t* __restrict__ out, uint32_t m) {
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u, g = lane >> 4, r = lane & 15u;
+    const uint32_t p0 = blockIdx.x * 128u, n0 = wave * 64u;
+    const __amdgpu_buffer_rsrc_t ri = rsrc(in, m * (uint32_t)(kW * 2));
+    const __amdgpu_buffer_rsrc_t rw = rsrc(w, (uint32_t)(kW * kW * 2));
+    const uint32_t aoff = (n0 + r) * (kW * 2) + g * 16u;
+    const uint32_t boff = (p0 + r) * (kW * 2) + g * 16u;
+    f4 acc[4][8];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const f4 bv = *reinterpret_cast<const f4*>(bias + n0 + 16 * mt + 4 * g);
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = bv;
+    }
+    u32x4 A[2][4], B[2][8];
+    auto load = [&](int buf, uint32_t kb) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            A[buf][mt] = __builtin_amdgcn_raw_buffer_load_b128(rw, aoff, mt * 16 * kW * 2 + kb * 64, 0);
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt)
+            B[buf][nt] = __builtin_amdgcn_raw_buffer_load_b128(ri, boff, nt * 16 * kW * 2 + kb * 64, 0);
+    };
+    auto step = [&](int buf) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = mma(A[buf][mt], B[buf][nt], acc[mt][nt]);
+    };
+    load(0, 0);
+#pragma unroll 1
+    for (uint32_t kb = 0; kb < kW / 32; kb += 2) {
+        load(1, kb + 1);
+        step(0);
+        if (kb + 2 < kW / 32) load(0, kb + 2);
+        step(1);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt) {
+        const uint32_t p = p0 + 16 * nt + r;
+        if (p >= m) continue;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const size_t at = (size_t)p * kW + n0 + 16 * mt + 4 * g;
+            f4 v = acc[mt][nt];
+            if constexpr (RES) {
+                const u32x2 xr = *reinterpret_cast<const u32x2*>(res + at);
+                v[0] += bf16_lo(xr[0]);
+                v[1] += bf16_hi(xr[0]);
+                v[2] += bf16_lo(xr[1]);
+                v[3] += bf16_hi(xr[1]);
+            }
+            *reinterpret_cast<u32x2*>(out + at) =
+                (u32x2){relu_bf16x2(pack_bf16(v[0], v[1])), relu_bf16x2(pack_bf16(v[2], v[3]))};
+        }
+    }
+}
+
+// Output layer (C <= 32 scores, no activation) and top-k. Workgroup: 4 waves, each 64
+// headers (4 column tiles) x 32 classes (2 row tiles). A header's 32 scores sit in the 4
+// lanes c, c+16, c+32, c+48 (8 each); ties go to the lower class.
+__global__ __launch_bounds__(256) void k_res_out(const uint16_t* __restrict__ in,
+                                                 const uint16_t* __restrict__ w,
+                                                 const float* __restrict__ bias, uint32_t m,
+                                                 int C, int topk, uint32_t* __restrict__ cand,
+                                                 float* __restrict__ logits,
+                                                 uint8_t* __restrict__ cand8) {
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u, g = lane >> 4, r = lane & 15u;
+    const uint32_t p0 = (blockIdx.x * 4u + wave) * 64u;
+    const __amdgpu_buffer_rsrc_t ri = rsrc(in, m * (uint32_t)(kW * 2));
+    const __amdgpu_buffer_rsrc_t rw = rsrc(w, (uint32_t)(32 * kW * 2));
+    const uint32_t aoff = r * (kW * 2) + g * 16u;
+    const uint32_t boff = (p0 + r) * (kW * 2) + g * 16u;
+    f4 acc[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        const f4 bv = *reinterpret_cast<const f4*>(bias + 16 * mt + 4 * g);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = bv;
+    }
+#pragma unroll 2
+    for (uint32_t kb = 0; kb < kW / 32; ++kb) {
+        u32x4 A[2], B[4];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+            A[mt] = __builtin_amdgcn_raw_buffer_load_b128(rw, aoff, mt * 16 * kW * 2 + kb * 64, 0);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+            B[nt] = __builtin_amdgcn_raw_buffer_load_b128(ri, boff, nt * 16 * kW * 2 + kb * 64, 0);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mma(A[mt], B[nt], acc[mt][nt]);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const uint32_t pkt = p0 + 16 * nt + r;
+        float v[8];
+        int cl[8];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = 16 * mt + 4 * (int)g + q;
+                const float val = acc[mt][nt][q];
+                if (logits && pkt < m && c < C) logits[(size_t)pkt * C + c] = val;
+                v[4 * mt + q] = (c < C && val == val) ? val : -INFINITY;
+                cl[4 * mt + q] = c;
+            }
+        uint32_t packed = 0;
+        for (int k = 0; k < topk; ++k) {
+            float bv = v[0];
+            int bc = cl[0];
+#pragma unroll
+            for (int q = 1; q < 8; ++q)
+                if (v[q] > bv) { bv = v[q]; bc = cl[q]; }  // classes ascend within a lane
+#pragma unroll
+            for (int o = 16; o <= 32; o <<= 1) {
+                const float ov = __shfl_xor(bv, o, 64);
+                const int oc = __shfl_xor(bc, o, 64);
+                if (ov > bv || (ov == bv && oc < bc)) { bv = ov; bc = oc; }
+            }
+            packed |= (uint32_t)bc << (8 * k);
+            if (cand8 && g == 0 && pkt < m) cand8[(size_t)pkt * topk + k] = (uint8_t)bc;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (cl[q] == bc) { v[q] = -INFINITY; cl[q] = 1 << 20; }
+        }
+        if (cand && g == 0 && pkt < m) cand[pkt] = packed;
+    }
+}
+
+uint16_t to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return 0x7FC0;
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+}  // namespace
+
+int resnet_prepare(tang_ruleset_t* rs, const tang_resnet_desc_t* d, const float* const* W,
+                   const float* const* b, tang_precision_t p) {
+    if (!d || !W || !b) return fail(TANG_EINVAL, "NULL model argument");
+    const int C = (int)rs->sigs.size();
+    if (d->width != (uint32_t)kW) return fail(TANG_EINVAL, "residual model width must be 512");
+    if (d->n_blocks < 1 || d->n_blocks > 16) return fail(TANG_EINVAL, "n_blocks must be in 1..16");
+    if ((int)d->n_out != C || C < 1 || C > kOutPad)
+        return fail(TANG_EINVAL, "output width must equal the number of tuples (1..32)");
+    if (d->topk < 1 || d->topk > TANG_MAX_TOPK || (int)d->topk > C)
+        return fail(TANG_EINVAL, "topk must be in 1..min(4, C)");
+    if (p != TANG_BF16) return fail(TANG_EINVAL, "the residual model runs in BF16");
+    const int nb = (int)d->n_blocks, L = 2 + 2 * nb;
+    for (int l = 0; l < L; ++l)
+        if (!W[l] || !b[l]) return fail(TANG_EINVAL, "NULL weight or bias");
+
+    ModelDev m;
+    m.kind = 1;
+    m.prec = p;
+    m.hidden = kW;
+    m.n_out = C;
+    m.topk = (int)d->topk;
+    m.n_blocks = nb;
+    std::vector<float> win((size_t)kW * 8, 0.0f);
+    for (int n = 0; n < kW; ++n)
+        for (int q = 0; q < 7; ++q) win[(size_t)n * 8 + q] = W[0][(size_t)n * 7 + q];
+    // biases: input layer, 2 per block, output (32, zero past C)
+    std::vector<float> bias((size_t)(1 + 2 * nb) * kW + kOutPad, 0.0f);
+    for (int l = 0; l < 1 + 2 * nb; ++l)
+        for (int n = 0; n < kW; ++n) bias[(size_t)l * kW + n] = b[l][n];
+    for (int c = 0; c < C; ++c) bias[(size_t)(1 + 2 * nb) * kW + c] = b[L - 1][c];
+    // BF16 weights: the block layers [512][512] each, then the output layer [32][512]
+    std::vector<uint16_t> w((size_t)2 * nb * kW * kW + (size_t)kOutPad * kW, 0);
+    for (int l = 0; l < 2 * nb; ++l)
+        for (size_t k = 0; k < (size_t)kW * kW; ++k) w[(size_t)l * kW * kW + k] = to_bf16(W[1 + l][k]);
+    for (int c = 0; c < C; ++c)
+        for (int k = 0; k < kW; ++k)
+            w[(size_t)2 * nb * kW * kW + (size_t)c * kW + k] = to_bf16(W[L - 1][(size_t)c * kW + k]);
+
+    hipError_t e = hipMalloc(&m.rin, win.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(m.rin, win.data(), win.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&m.bias, bias.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(m.bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&m.rw, w.size() * 2);
+    if (e == hipSuccess) e = hipMemcpy(m.rw, w.data(), w.size() * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&m.ws, (size_t)3 * kChunk * kW * 2);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m.ws_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        model_free(m);
+        return hip_fail(e, "residual model upload");
+    }
+    m.bytes = win.size() * 4 + bias.size() * 4 + w.size() * 2 + (size_t)3 * kChunk * kW * 2;
+    m.loaded = 1;
+    model_free(rs->model);
+    rs->model = m;
+    rs->version++;
+    return TANG_OK;
+}
+
+// The workspace is shared by every call on this ruleset: each call's launches wait for
+// the previous call's (an event), whatever stream either used.
+hipError_t launch_resnet(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
+                         uint32_t* cand, float* logits, uint8_t* cand8, hipStream_t s) {
+    const ModelDev& m = rs->model;
+    std::lock_guard<std::mutex> lk(rs->ws_mu);
+    hipError_t e = hipSuccess;
+    if (m.ws_used) e = hipStreamWaitEvent(s, m.ws_done, 0);
+    if (e != hipSuccess) return e;
+    const int nb = m.n_blocks;
+    const uint16_t* wts = static_cast<const uint16_t*>(m.rw);
+    const uint16_t* wout = wts + (size_t)2 * nb * kW * kW;
+    const float* bout = m.bias + (size_t)(1 + 2 * nb) * kW;
+    for (size_t base = 0; base < n; base += kChunk) {
+        const uint32_t c = (uint32_t)std::min<size_t>(kChunk, n - base);
+        uint16_t* X = m.ws;
+        uint16_t* Hm = X + (size_t)kChunk * kW;
+        uint16_t* Y = Hm + (size_t)kChunk * kW;
+        const uint32_t gin = std::min<uint32_t>((c + 3) / 4, 2048);
+        hipLaunchKernelGGL(k_res_input, dim3(gin), dim3(256), 0, s,
+                           reinterpret_cast<const uint4*>(d_hdr + base), c, m.rin, m.bias,
+                           reinterpret_cast<u32x4*>(X));
+        const dim3 gd((c + 127) / 128);
+        for (int k = 0; k < nb; ++k) {
+            const uint16_t* w1 = wts + (size_t)(2 * k) * kW * kW;
+            const uint16_t* w2 = w1 + (size_t)kW * kW;
+            const float* b1 = m.bias + (size_t)(1 + 2 * k) * kW;
+            const float* b2 = b1 + kW;
+            hipLaunchKernelGGL(k_res_dense<false>, gd, dim3(512), 0, s, X, w1, b1, nullptr, Hm, c);
+            hipLaunchKernelGGL(k_res_dense<true>, gd, dim3(512), 0, s, Hm, w2, b2, X, Y, c);
+            std::swap(X, Y);
+        }
+        hipLaunchKernelGGL(k_res_out, dim3((c + 255) / 256), dim3(256), 0, s, X, wout, bout, c,
+                           m.n_out, m.topk, cand ? cand + base : nullptr,
+                           logits ? logits + base * (size_t)m.n_out : nullptr,
+                           cand8 ? cand8 + base * (size_t)m.topk : nullptr);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    e = hipEventRecord(m.ws_done, s);
+    if (e == hipSuccess) m.ws_used = true;
+    return e;
+}
+
+}  // namespace tang

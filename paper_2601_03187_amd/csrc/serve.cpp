@@ -141,7 +141,9 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, std::vector<std::shared_ptr
         TANG_HIP(hipStreamSynchronize(s.stream));
         warmed[tag] = 1;
     }
-    if (cfg.use_graphs) {
+    // the residual predictor orders its shared workspace with an event across calls, which
+    // a captured graph cannot hold: its batches run eagerly
+    if (cfg.use_graphs && rs->model.kind == 0) {
         hipGraphExec_t exec = nullptr;
         int rc = graph_for(tag, (uint32_t)cls, si, &exec);
         if (rc) return rc;

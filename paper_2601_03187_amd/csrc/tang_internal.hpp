@@ -135,6 +135,7 @@ constexpr int kInPad = 128;   // 104 input bits padded to 128
 
 struct ModelDev {
     int loaded = 0;
+    int kind = 0;     // 0: the plain 104 -> H -> H -> C network; 1: the residual network
     tang_precision_t prec = TANG_FP32;
     int hidden = 0;
     int n_out = 0;    // C
@@ -145,6 +146,14 @@ struct ModelDev {
     float* bias = nullptr;   // [hidden | hidden | 32] floats
     float deq[3] = {1, 1, 1};     // FP8: s_a * s_w per layer
     float inv_a[3] = {1, 1, 1};   // FP8: 1 / s_a per layer (layer 0 unused)
+    // Residual network: input layer FP32 [512][8], BF16 layer weights, BF16 activation
+    // workspace (three chunk buffers) and the event that orders calls sharing it.
+    int n_blocks = 0;
+    float* rin = nullptr;
+    void* rw = nullptr;
+    uint16_t* ws = nullptr;
+    hipEvent_t ws_done = nullptr;
+    mutable bool ws_used = false;
     size_t bytes = 0;
 };
 
@@ -199,6 +208,7 @@ struct tang_ruleset_s {
     hipStream_t upd_stream = nullptr;
     tang::ModelDev model;
     std::mutex stats_mu;
+    mutable std::mutex ws_mu;  // enqueueing of residual-model launches (shared workspace)
     // Chunked classify: the searches of a large batch run on this stream (created on first
     // use, default priority), each after its chunk's model on the caller's stream.
     std::mutex pipe_mu;
@@ -252,6 +262,10 @@ int classify_async(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_r
 hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
                       uint32_t* d_cand_packed, float* d_logits, uint8_t* d_cand8,
                       hipStream_t s);
+int resnet_prepare(tang_ruleset_t* rs, const tang_resnet_desc_t* d, const float* const* W,
+                   const float* const* b, tang_precision_t p);
+hipError_t launch_resnet(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
+                         uint32_t* cand, float* logits, uint8_t* cand8, hipStream_t s);
 int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* const* W,
                   const float* const* b, tang_precision_t p, const float* act_scales);
 void model_free(ModelDev& m);

@@ -38,6 +38,11 @@ class tang_mlp_desc_t(ctypes.Structure):
     _fields_ = [("n_layers", ctypes.c_uint32), ("dims", ctypes.c_uint32 * 9), ("topk", ctypes.c_uint32)]
 
 
+class tang_resnet_desc_t(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_uint32), ("n_blocks", ctypes.c_uint32), ("n_out", ctypes.c_uint32),
+                ("topk", ctypes.c_uint32)]
+
+
 class tang_stats_t(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in
                 ("packets", "probes", "slots", "records", "top1_hits", "fallbacks", "no_match",
@@ -78,6 +83,7 @@ _sigs = {
     "tang_ruleset_device_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "tang_ruleset_set_stream": (ctypes.c_int, [_P, _P]),
     "tang_model_load": (ctypes.c_int, [_P, ctypes.POINTER(tang_mlp_desc_t), _P, _P, ctypes.c_int, _P]),
+    "tang_model_load_resnet": (ctypes.c_int, [_P, ctypes.POINTER(tang_resnet_desc_t), _P, _P, ctypes.c_int]),
     "tang_model_unload": (ctypes.c_int, [_P]),
     "tang_classify": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, _P, ctypes.POINTER(tang_stats_t)]),
     "tang_predict": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, _P]),
@@ -206,6 +212,18 @@ def tang_model_load(rs: int, Ws, bs, precision="fp32", topk: int = 1, act_scales
         sc = np.ascontiguousarray(np.asarray(act_scales, dtype=np.float32))
     _check(_lib.tang_model_load(rs, ctypes.byref(d), ctypes.cast(wp, _P), ctypes.cast(bp, _P), p,
                                 sc.ctypes.data if sc is not None else None))
+
+
+def tang_model_load_resnet(rs: int, Ws, bs, precision="bf16", topk: int = 1) -> None:
+    """The residual predictor: Ws = [W_in (width x 7), then two width x width matrices per
+    block, W_out (C x width)], nn.Linear layout; bs likewise."""
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    Ws = [np.ascontiguousarray(np.asarray(w, dtype=np.float32)) for w in Ws]
+    bs = [np.ascontiguousarray(np.asarray(b, dtype=np.float32)) for b in bs]
+    d = tang_resnet_desc_t(Ws[0].shape[0], (len(Ws) - 2) // 2, Ws[-1].shape[0], topk)
+    wp = (ctypes.c_void_p * len(Ws))(*[w.ctypes.data for w in Ws])
+    bp = (ctypes.c_void_p * len(bs))(*[b.ctypes.data for b in bs])
+    _check(_lib.tang_model_load_resnet(rs, ctypes.byref(d), ctypes.cast(wp, _P), ctypes.cast(bp, _P), p))
 
 
 def tang_model_unload(rs: int) -> None:
