@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-literal", action="store_true")
     ap.add_argument("--skip-probe-all", action="store_true")
+    ap.add_argument("--skip-resnet", action="store_true",
+                    help="skip the paper-size residual predictor (7 -> 512 -> 6 blocks -> C)")
     ap.add_argument("--skip-configs", action="store_true",
                     help="skip the 1k / 64k configurations and the 80%%-rule-sampled 512k run")
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
@@ -243,6 +245,10 @@ def main():
         T.tang_model_load(rs, Ws, bs, base, topk=1, act_scales=sc if base == "fp8" else None)
         configs = other_configs(args, rules, rs, d_hdr, base)
 
+    resnet = None
+    if not args.skip_resnet:
+        resnet = bench_resnet(args, rs, d_hdr, d_out, got_by_prec[base], C)
+
     # oracle: CPU baseline on a bounded seeded sample, and the bit-exact check
     cpu = None
     exact = None
@@ -300,6 +306,7 @@ def main():
         "roofline": roof, "kernels": other,
         "per_precision": per, "candidate_change_vs_fp32": cand_change,
         "literal_ordering": lit, "no_model_probe_all": probe_all, "other_configs": configs,
+        "paper_resnet_predictor": resnet,
         "build_s": build_s, "train_top1": acc,
         "cpu_baseline": cpu,
         "paper_context": "TaNG reports 10.98 Mpps average at 512k rules (12 ClassBench-ng rulesets, "
@@ -395,6 +402,48 @@ def other_configs(args, rules3, rs3, d_hdr3, prec3):
                                    "oracle_checked": int(len(samp)),
                                    "mismatches": int((got[samp] != want).sum())}
     log(f"[bench] c3 with 80% rule-sampled headers: {res['c3_512k_80pct_inside']['mpps']:.0f} Mpps")
+    return res
+
+
+def bench_resnet(args, rs, d_hdr, d_out, want, C):
+    """The paper's own predictor size (7 chunks -> 512 -> 6 residual blocks -> C, BF16,
+    random weights: speed only) on the first 4,194,304 headers of the 512k workload: the
+    predictor alone (tang_predict, HIP events) and whole classification (chunked, two
+    streams); the answers must equal the BF16 run's."""
+    import numpy as np
+    import torch
+
+    from paper_2601_03187_amd import tang as T
+
+    n = 1 << 22
+    rng = np.random.default_rng(77)
+    width, nb = 512, 6
+    Ws = [rng.normal(0, 2.0, (width, 7))] + [rng.normal(0, 1 / np.sqrt(width), (width, width))
+                                              for _ in range(2 * nb)] + [rng.normal(0, 1 / np.sqrt(width), (C, width))]
+    bs = [rng.normal(0, 0.05, w.shape[0]) for w in Ws]
+    T.tang_model_load_resnet(rs, Ws, bs, "bf16", topk=1)
+    s = torch.cuda.current_stream()
+    T.tang_predict(rs, d_hdr, d_out, n, s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record(s)
+    for _ in range(reps):
+        T.tang_predict(rs, d_hdr, d_out, n, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    mlp_ms = e0.elapsed_time(e1) / reps
+    flop = 2 * (7 * width + 2 * nb * width * width + width * C)
+    T.tang_classify(rs, d_hdr, d_out, n, s)
+    torch.cuda.synchronize()
+    ok = bool(np.array_equal(d_out[:n].cpu().numpy().view(np.uint32), want[:n]))
+    ms = time_classify(T, rs, d_hdr, d_out, n, reps)
+    tflops = flop * n / (mlp_ms * 1e-3) / 1e12
+    res = {"headers": n, "blocks": nb, "width": width, "precision": "bf16", "weights": "random",
+           "flop_per_pkt": flop, "predict_ms": mlp_ms, "predict_mpps": n / mlp_ms / 1e3,
+           "predict_tflops": tflops, "predict_frac_of_bf16_peak": tflops / PEAK_TFLOPS["bf16"],
+           "classify_ms": ms, "classify_mpps": n / ms / 1e3, "answers_equal_bf16_run": ok}
+    log(f"[bench] residual predictor (6 x 512): predict {res['predict_mpps']:.0f} Mpps "
+        f"({tflops:.0f} TFLOP/s), classify {res['classify_mpps']:.0f} Mpps, answers equal: {ok}")
     return res
 
 

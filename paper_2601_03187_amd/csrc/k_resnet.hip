@@ -97,21 +97,30 @@ __global__ __launch_bounds__(256) void k_res_input(const uint4* __restrict__ hdr
 // One 512 x 512 layer: out = relu(W in + b [+ res]) over m header rows, BF16 in and out,
 // FP32 accumulation with the bias as the accumulator's start. Workgroup: 8 waves and 128
 // headers; wave w computes neurons 64w..64w+63 (4 row tiles) for all 128 headers (8 column
-// tiles). K advances 32 at a time with the next step's fragments loaded before the
-// current step's 32 MFMAs. Rows past m read as zero (buffer range check) and are not
-// written.
+// tiles). K advances 32 at a time. The headers' 32-wide K slice (128 x 64 bytes) is
+// shared by the 8 waves through LDS -- each thread copies 16 bytes of the next slice while
+// the current one is multiplied (double buffer, one barrier per step); rows are padded to
+// 80 bytes so that the 16 lanes of a 128-bit read hit 16 distinct groups of 4 banks. Each
+// wave reads its own weight rows straight from L2. Global loads of both operands are
+// issued two steps ahead (the activations come from the Infinity Cache or HBM). Rows past
+// m read as zero (buffer range check) and are not written.
+constexpr uint32_t kRowB = 80;   // bytes per header row of a K slice in LDS (64 + 16 pad)
+
 template <bool RES>
 __global__ __launch_bounds__(512) void k_res_dense(const uint16_t* __restrict__ in,
                                                    const uint16_t* __restrict__ w,
                                                    const float* __restrict__ bias,
                                                    const uint16_t* __restrict__ res,
                                                    uint16_t* __restrict__ out, uint32_t m) {
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u, g = lane >> 4, r = lane & 15u;
+    __shared__ __attribute__((aligned(16))) unsigned char sb[2][128 * kRowB];
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u, g = lane >> 4, r = lane & 15u;
     const uint32_t p0 = blockIdx.x * 128u, n0 = wave * 64u;
     const __amdgpu_buffer_rsrc_t ri = rsrc(in, m * (uint32_t)(kW * 2));
     const __amdgpu_buffer_rsrc_t rw = rsrc(w, (uint32_t)(kW * kW * 2));
     const uint32_t aoff = (n0 + r) * (kW * 2) + g * 16u;
-    const uint32_t boff = (p0 + r) * (kW * 2) + g * 16u;
+    // this thread's share of a K slice: header tid / 4, bytes 16 (tid % 4) .. + 15
+    const uint32_t coff = (p0 + (tid >> 2)) * (kW * 2) + (tid & 3u) * 16u;
+    const uint32_t cdst = (tid >> 2) * kRowB + (tid & 3u) * 16u;
     f4 acc[4][8];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
@@ -119,28 +128,32 @@ __global__ __launch_bounds__(512) void k_res_dense(const uint16_t* __restrict__ 
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = bv;
     }
-    u32x4 A[2][4], B[2][8];
-    auto load = [&](int buf, uint32_t kb) {
+    // loads run kD steps ahead through a ring of kR register slots (fully unrolled, so
+    // every slot index is a constant)
+    constexpr int kS = kW / 32, kD = 2, kR = kD + 1;
+    u32x4 A[kR][4], Bq[kR];
+    auto issue = [&](int kb) {
+        Bq[kb % kR] = __builtin_amdgcn_raw_buffer_load_b128(ri, coff, kb * 64, 0);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
-            A[buf][mt] = __builtin_amdgcn_raw_buffer_load_b128(rw, aoff, mt * 16 * kW * 2 + kb * 64, 0);
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt)
-            B[buf][nt] = __builtin_amdgcn_raw_buffer_load_b128(ri, boff, nt * 16 * kW * 2 + kb * 64, 0);
+            A[kb % kR][mt] = __builtin_amdgcn_raw_buffer_load_b128(rw, aoff, mt * 16 * kW * 2 + kb * 64, 0);
     };
-    auto step = [&](int buf) {
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+    for (int kb = 0; kb < kD; ++kb) issue(kb);
+    *reinterpret_cast<u32x4*>(sb[0] + cdst) = Bq[0];
+    __syncthreads();
 #pragma unroll
-            for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = mma(A[buf][mt], B[buf][nt], acc[mt][nt]);
-    };
-    load(0, 0);
-#pragma unroll 1
-    for (uint32_t kb = 0; kb < kW / 32; kb += 2) {
-        load(1, kb + 1);
-        step(0);
-        if (kb + 2 < kW / 32) load(0, kb + 2);
-        step(1);
+    for (int kb = 0; kb < kS; ++kb) {
+        if (kb + kD < kS) issue(kb + kD);
+        const unsigned char* bt = sb[kb & 1];
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+            const u32x4 B = *reinterpret_cast<const u32x4*>(bt + (16 * nt + r) * kRowB + g * 16);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) acc[mt][nt] = mma(A[kb % kR][mt], B, acc[mt][nt]);
+        }
+        if (kb + 1 < kS) *reinterpret_cast<u32x4*>(sb[(kb + 1) & 1] + cdst) = Bq[(kb + 1) % kR];
+        __syncthreads();
     }
 #pragma unroll
     for (int nt = 0; nt < 8; ++nt) {
