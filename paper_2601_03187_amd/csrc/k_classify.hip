@@ -100,7 +100,7 @@ __device__ __forceinline__ void search_tuple(uint32_t t, uint64_t h, uint32_t ms
     }
 }
 
-// Searches tuple t for this header after checking its filter bit (one hash serves both).
+// Searches tuple t for this header after checking its filter bit.
 template <bool STATS>
 __device__ __forceinline__ void probe(uint32_t t, uint32_t sip, uint32_t dip, uint32_t sp,
                                       uint32_t dp, uint32_t proto, const TupleDev* s_t,
@@ -110,12 +110,11 @@ __device__ __forceinline__ void probe(uint32_t t, uint32_t sip, uint32_t dip, ui
                                       Best& b, uint32_t& n_probe, uint32_t& n_slots,
                                       uint32_t& n_recs, uint32_t& n_filter) {
     const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
-    const uint64_t h = key_hash(t, ms, md);
-    const uint32_t bit = filter_of(h) & filter_mask;
+    const uint32_t bit = filter_hash(t, ms, md) & filter_mask;
     if (STATS) ++n_filter;
     if (!((filter[bit >> 5] >> (bit & 31u)) & 1u)) return;
-    search_tuple<STATS>(t, h, ms, md, sip, dip, sp, dp, proto, slot_mask, slots, recs, b, n_probe,
-                        n_slots, n_recs);
+    search_tuple<STATS>(t, key_hash(t, ms, md), ms, md, sip, dip, sp, dp, proto, slot_mask, slots,
+                        recs, b, n_probe, n_slots, n_recs);
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
@@ -221,7 +220,7 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
             pos[q] = 0;
             if ((todo >> t) & 1u) {  // t < ntup: todo holds only existing tuples
                 const uint32_t bit =
-                    filter_of(key_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask)) & filter_mask;
+                    filter_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask) & filter_mask;
                 w[q] = filter[bit >> 5];
                 pos[q] = bit & 31u;
                 if (STATS) ++n_filter;

@@ -90,8 +90,8 @@ struct TupleTable {
 // Key hash: two chained MurmurHash3 32-bit finalisers (fmix32, Appleby, public domain),
 // first over the masked SIP salted by the tuple index, then over that result xor the
 // masked DIP. Each stage is a bijection, so structured keys (prefixes whose only varying
-// bits are the top byte) do not collapse. The low half of the result picks the slot; the
-// high half, a further xorshift-multiply of it, picks the filter bit.
+// bits are the top byte) do not collapse. The low half of the result picks the slot.
+// The bucket filter uses its own cheaper hash (filter_hash below).
 __host__ __device__ inline uint32_t fmix32(uint32_t h) {
     h ^= h >> 16;
     h *= 0x85EBCA6Bu;
@@ -107,9 +107,20 @@ __host__ __device__ inline uint64_t key_hash(uint32_t t, uint32_t ms, uint32_t m
     return ((uint64_t)f << 32) | h;
 }
 __host__ __device__ inline uint32_t slot_of(uint64_t h) { return (uint32_t)h; }
-__host__ __device__ inline uint32_t filter_of(uint64_t h) { return (uint32_t)(h >> 32); }
+// Filter bit of a key: the masked SIP xor the masked DIP rotated by 13 (so the /8 and /16
+// prefixes of the two fields land on different bits) xor a tuple salt, then two
+// multiply-xorshift rounds. Only placement of filter bits depends on it (a collision can
+// only set a bit that a lookup then checks in vain), and it costs a third of key_hash.
+__host__ __device__ inline uint32_t filter_hash(uint32_t t, uint32_t ms, uint32_t md) {
+    uint32_t x = ms ^ ((md << 13) | (md >> 19)) ^ ((t + 1u) * 0x9E3779B9u);
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 15;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return x;
+}
 
-// Bucket filter: one bit per filter_of(key) over all buckets ever created (a superset
+// Bucket filter: one bit per filter_hash(key) over all buckets ever created (a superset
 // after deletes). A header's masked key whose bit is clear has no bucket in that tuple,
 // so the slot walk is skipped; at >= 32 bits per bucket about 3% of absent keys pass.
 // Sized to stay L2-resident (2 MB at 512k rules).

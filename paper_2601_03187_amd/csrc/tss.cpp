@@ -75,7 +75,7 @@ std::vector<uint32_t> split_bucket(tang_ruleset_t* rs, uint32_t b) {
 }
 
 void filter_set(std::vector<uint32_t>& f, uint32_t t, uint32_t ms, uint32_t md) {
-    const uint32_t b = filter_of(key_hash(t, ms, md)) & ((uint32_t)f.size() * 32u - 1u);
+    const uint32_t b = filter_hash(t, ms, md) & ((uint32_t)f.size() * 32u - 1u);
     f[b >> 5] |= 1u << (b & 31u);
 }
 
