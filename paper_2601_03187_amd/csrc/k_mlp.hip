@@ -86,7 +86,10 @@ __device__ __forceinline__ uint32_t hword(const uint4& h, int w) {
     return w == 0 ? h.x : w == 1 ? h.y : w == 2 ? ((h.z << 16) | (h.z >> 16)) : ((h.w & 0xFFu) << 24);
 }
 
-// B fragment of the input bits for K block kb and lane group g.
+// B fragment of the input bits for K block kb and lane group g. BF16 and FP8 read it
+// from a 256-entry table in LDS indexed by a header byte (one extract and one LDS read
+// per byte instead of a chain of per-bit operations); the table entries are made by
+// `bits_entry`, the same per-bit rule the FP32 path applies directly.
 template <int PREC> struct Bits;
 template <> struct Bits<TANG_FP32> {
     // feature f = 4kb + g: byte kb/2, bit (from the MSB) 4(kb&1) + g
@@ -98,29 +101,46 @@ template <> struct Bits<TANG_FP32> {
     }
 };
 template <> struct Bits<TANG_BF16> {
-    // features 32kb + 8g + j (j = 0..7): byte 4kb + g, bit (from the MSB) j
-    __device__ static __forceinline__ u32x4 get(const uint4& h, int kb, int g) {
-        const uint32_t byte = (hword(h, kb) >> (24 - 8 * g)) & 0xFFu;
+    // features 32kb + 8g + j (j = 0..7): byte 4kb + g, bit (from the MSB) j; a table entry
+    // is 4 words, each two BF16 (1.0 = 0x3F80) for bits 2w and 2w + 1 of the byte
+    static constexpr int kEntry = 16;
+    __device__ static __forceinline__ void entry(uint32_t byte, unsigned char* dst) {
         u32x4 r;
 #pragma unroll
         for (int w = 0; w < 4; ++w)
             r[w] = ((byte >> (7 - 2 * w)) & 1u) * 0x3F80u | ((byte >> (6 - 2 * w)) & 1u) * 0x3F800000u;
-        return r;
+        *reinterpret_cast<u32x4*>(dst) = r;
+    }
+    __device__ static __forceinline__ u32x4 get(const uint4& h, int kb, int g, const unsigned char* tab) {
+        const uint32_t byte = (hword(h, kb) >> (24 - 8 * g)) & 0xFFu;
+        return *reinterpret_cast<const u32x4*>(tab + byte * kEntry);
     }
 };
 template <> struct Bits<TANG_FP8> {
     // K = 128 in one block: features 32g + j (j = 0..31) are the bits of header word g,
-    // most significant first; 1.0 in E4M3 is 0x38
-    __device__ static __forceinline__ u32x8 get(const uint4& h, int, int g) {
+    // most significant first; 1.0 in E4M3 is 0x38. A table entry is the 8 bytes of one
+    // header byte's bits (two words of the fragment).
+    static constexpr int kEntry = 8;
+    __device__ static __forceinline__ void entry(uint32_t byte, unsigned char* dst) {
+        u32x2 r;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) v |= ((byte >> (7 - 4 * half - b)) & 1u) * (0x38u << (8 * b));
+            r[half] = v;
+        }
+        *reinterpret_cast<u32x2*>(dst) = r;
+    }
+    __device__ static __forceinline__ u32x8 get(const uint4& h, int, int g, const unsigned char* tab) {
         const uint32_t w = g == 0 ? h.x : g == 1 ? h.y : g == 2 ? ((h.z << 16) | (h.z >> 16))
                                                                 : ((h.w & 0xFFu) << 24);
         u32x8 r;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            uint32_t v = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) v |= ((w >> (31 - (4 * q + b))) & 1u) * (0x38u << (8 * b));
-            r[q] = v;
+        for (int k = 0; k < 4; ++k) {
+            const u32x2 e = *reinterpret_cast<const u32x2*>(tab + ((w >> (24 - 8 * k)) & 0xFFu) * kEntry);
+            r[2 * k] = e[0];
+            r[2 * k + 1] = e[1];
         }
         return r;
     }
@@ -218,6 +238,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
     F* s2 = s1 + ((LDSM & 1) ? n1 : 0);
     F* s3 = s2 + ((LDSM & 2) ? n2 : 0);
     float* sb = reinterpret_cast<float*>(s3 + ((LDSM & 4) ? n3 : 0));
+    unsigned char* stab = reinterpret_cast<unsigned char*>(sb + nb);  // BF16 / FP8 bit table
 
     {   // stage resident weights and the biases
         auto copy16 = [&](void* dst, const void* src, uint32_t bytes) {
@@ -229,6 +250,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
         if (LDSM & 2) copy16(s2, w2, n2 * sizeof(F));
         if (LDSM & 4) copy16(s3, w3, n3 * sizeof(F));
         copy16(sb, bias_g, nb * sizeof(float));
+        if constexpr (PREC != TANG_FP32)
+            if (threadIdx.x < 256) Bits<PREC>::entry(threadIdx.x, stab + threadIdx.x * Bits<PREC>::kEntry);
     }
     __syncthreads();
 
@@ -262,7 +285,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
 #pragma unroll
             for (int kb = 0; kb < KBN1_USED; ++kb)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) bits[kb][nt] = Bits<PREC>::get(hv[nt], kb, g);
+                for (int nt = 0; nt < NT; ++nt) bits[kb][nt] = Bits<PREC>::get(hv[nt], kb, g, stab);
         }
         if constexpr (!(LDSM & 1)) {
 #pragma unroll
@@ -546,7 +569,8 @@ hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, u
     constexpr size_t n1 = (H / 16) * (kInPad / KB) * 64, n2 = (H / 16) * (H / KB) * 64,
                      n3 = 2 * (H / KB) * 64;
     const size_t lds = ((LDSM & 1) ? n1 : 0) * sizeof(F) + ((LDSM & 2) ? n2 : 0) * sizeof(F) +
-                       ((LDSM & 4) ? n3 : 0) * sizeof(F) + (2 * H + kOutPad) * sizeof(float);
+                       ((LDSM & 4) ? n3 : 0) * sizeof(F) + (2 * H + kOutPad) * sizeof(float) +
+                       (PREC == TANG_BF16 ? 256 * 16 : PREC == TANG_FP8 ? 256 * 8 : 0);
     auto kern = k_mlp<PREC, H, NT, LDSM, WAVES>;
     static int attr_done = 0;  // per instantiation
     if (!attr_done) {
