@@ -69,6 +69,9 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-literal", action="store_true")
     ap.add_argument("--skip-probe-all", action="store_true")
+    ap.add_argument("--skip-stats", action="store_true",
+                    help="skip the paper's training loop and its statistics (model accuracy, "
+                         "classification accuracy of the paper's own search, memory accesses)")
     ap.add_argument("--skip-resnet", action="store_true",
                     help="skip the paper-size residual predictor (7 -> 512 -> 6 blocks -> C)")
     ap.add_argument("--skip-configs", action="store_true",
@@ -245,6 +248,10 @@ def main():
         T.tang_model_load(rs, Ws, bs, base, topk=1, act_scales=sc if base == "fp8" else None)
         configs = other_configs(args, rules, rs, d_hdr, base)
 
+    stats = None
+    if not args.skip_stats:
+        stats = paper_statistics(args, rules, rs, hdr, d_hdr, d_out, got_by_prec[base], C)
+
     resnet = None
     if not args.skip_resnet:
         resnet = bench_resnet(args, rs, d_hdr, d_out, got_by_prec[base], C)
@@ -306,7 +313,7 @@ def main():
         "roofline": roof, "kernels": other,
         "per_precision": per, "candidate_change_vs_fp32": cand_change,
         "literal_ordering": lit, "no_model_probe_all": probe_all, "other_configs": configs,
-        "paper_resnet_predictor": resnet,
+        "paper_resnet_predictor": resnet, "paper_statistics": stats,
         "build_s": build_s, "train_top1": acc,
         "cpu_baseline": cpu,
         "paper_context": "TaNG reports 10.98 Mpps average at 512k rules (12 ClassBench-ng rulesets, "
@@ -403,6 +410,68 @@ def other_configs(args, rules3, rs3, d_hdr3, prec3):
                                    "mismatches": int((got[samp] != want).sum())}
     log(f"[bench] c3 with 80% rule-sampled headers: {res['c3_512k_80pct_inside']['mpps']:.0f} Mpps")
     return res
+
+
+def paper_statistics(args, rules, rs, hdr, d_hdr, d_out, want, C):
+    """Analogue of the paper's statistics tables (Sec. 7.5) on the 512k workload, for the
+    plain predictor and the paper's residual network, each trained with the paper's loop
+    (alpha oversampling, beta = 0.95, rounds of epochs; reduced epochs) on the first
+    1,048,576 headers: model accuracy (top-1 tuple = tuple of the exact answer) on the last
+    1,048,576 headers (held out); classification accuracy of the paper's own search (the
+    best rule of the predicted tuple if one matches, else the ordered search over the other
+    tuples, without certification) on a seeded sample of 20,000 held-out headers, from the
+    oracle restricted to each predicted tuple; this library's accuracy (its answers equal
+    the oracle's); tuples; and memory accesses per lookup (filter words, slots, records)."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as orc
+    from paper_2601_03187_amd import train
+    from paper_2601_03187_amd import tang as T
+
+    n = len(hdr)
+    ntr = 1 << 20
+    held = np.arange(n - ntr, n)
+    tup_of_rule = train.tuple_labels(rs, rules, rules["id"])
+    label = train.tuple_labels(rs, rules, want[held])
+    samp = np.sort(np.random.default_rng(13).choice(held, 20_000, replace=False))
+    truth = want[samp]
+    out = {"tuples": C}
+    s = torch.cuda.current_stream()
+    for arch, width, kw in (("mlp", 256, {}), ("resnet", 512, {"n_blocks": 6})):
+        t0 = time.time()
+        Ws, bs, info = train.train_paper(rs, rules, hdr[:ntr], arch=arch, hidden=width, alpha=1000,
+                                         beta=0.95, rounds=3, epochs=10, device="cuda",
+                                         rule_ids=want[:ntr], **kw)
+        if arch == "mlp":
+            T.tang_model_load(rs, Ws, bs, "bf16", topk=1)
+        else:
+            T.tang_model_load_resnet(rs, Ws, bs, "bf16", topk=1)
+        cand = torch.empty(n, dtype=torch.uint8, device="cuda")
+        T.tang_mlp_forward(rs, d_hdr, n, None, cand, s)
+        pred = cand.cpu().numpy().astype(np.int64)
+        ok = label >= 0
+        model_acc = float(np.mean(pred[held][ok] == label[ok]))
+        # the paper's search: best match inside the predicted tuple, else the true answer
+        # (the ordered search over the remaining tuples finds the best of them)
+        paper = truth.copy()
+        ps = pred[samp]
+        for t in np.unique(ps):
+            g = ps == t
+            inside = orc.classify(rules, hdr[samp[g]], live=(tup_of_rule == t).astype(np.uint8))
+            paper[g] = np.where(inside != orc.NO_MATCH, inside, truth[g])
+        st = T.tang_classify(rs, d_hdr, d_out, n, s, want_stats=True)
+        exact = bool(np.array_equal(d_out.cpu().numpy().view(np.uint32), want))
+        out[arch] = {"train_rounds": info["rounds"], "converged": info["converged"],
+                     "train_s": time.time() - t0, "model_accuracy_heldout": model_acc,
+                     "paper_search_accuracy": float(np.mean(paper == truth)),
+                     "this_library_accuracy": 1.0 if exact else float(np.mean(d_out.cpu().numpy().view(np.uint32) == want)),
+                     "filter_words_per_lookup": st["filter_checks"] / n,
+                     "slots_per_lookup": st["slots"] / n, "records_per_lookup": st["records"] / n,
+                     "probes_per_lookup": st["probes"] / n}
+        log(f"[bench] paper loop, {arch}: model accuracy {model_acc:.4f}, paper search accuracy "
+            f"{out[arch]['paper_search_accuracy']:.5f}, exact {exact}, rounds {len(info['rounds'])}")
+    return out
 
 
 def bench_resnet(args, rs, d_hdr, d_out, want, C):

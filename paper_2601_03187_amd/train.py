@@ -1,11 +1,13 @@
 """Weights for the tuple predictor (tooling, outside the classify path).
 
-Training follows the recipe of Sec. 6.2 in reduced form: each packet's label is the
-tuple of its highest-priority matching rule, obtained here from the library's own exact
-classification; cross-entropy loss, Adam, batch 8192, learning rate 1e-3. The paper's
-class-balance loop (alpha oversampling, beta accuracy target, 1000-epoch rounds) is
-not run: the answers the library returns never depend on the weights, only the number
-of tuples probed does.
+Labels follow Sec. 6.2: each packet's label is the tuple of its highest-priority
+matching rule, obtained here from the library's own exact classification. ``fit`` trains
+the plain predictor in reduced form (cross-entropy, Adam, batch 8192, learning rate 1e-3,
+a fixed number of steps); ``train_paper`` runs the paper's whole loop: classes below a
+threshold alpha are oversampled up to alpha, rounds of epochs with the learning rate
+decayed by 0.1 every fifth of a round, and alpha multiplied by 10 after any round whose
+accuracy stays below beta. The answers the library returns never depend on the weights,
+only the number of tuples probed does.
 
 Also: the static per-layer activation scales for FP8 (amax of each hidden layer's
 output over a calibration batch, divided by 448) and random / degenerate weights used
@@ -32,6 +34,121 @@ def feature_bits_torch(hdr: np.ndarray, device="cpu"):
         shifts = torch.arange(width - 1, -1, -1, device=device)
         cols.append(((t[:, None] >> shifts[None, :]) & 1).to(torch.float32))
     return torch.cat(cols, dim=1)
+
+
+def segments_torch(hdr: np.ndarray, device="cpu"):
+    """(n, 7) float32 tensor of the residual predictor's input (Sec. 6.2): SIP high, SIP low,
+    DIP high, DIP low, SP, DP, PROTO, each divided by 65535."""
+    import torch
+    sip = hdr["sip"].astype(np.int64)
+    dip = hdr["dip"].astype(np.int64)
+    cols = [sip >> 16, sip & 0xFFFF, dip >> 16, dip & 0xFFFF, hdr["sp"].astype(np.int64),
+            hdr["dp"].astype(np.int64), hdr["proto"].astype(np.int64)]
+    return torch.as_tensor(np.stack(cols, axis=1), device=device).to(torch.float32) / 65535.0
+
+
+def _resnet_module(n_out: int, width: int, n_blocks: int):
+    """Sec. 6.1 with residual blocks: FC(7 -> width) + ReLU, blocks
+    relu(relu(x w1 + b1) w2 + b2 + x), FC(width -> C)."""
+    import torch
+
+    class Net(torch.nn.Module):
+        def __init__(self):
+            super().__init__()
+            self.inp = torch.nn.Linear(7, width)
+            self.blocks = torch.nn.ModuleList(
+                [torch.nn.ModuleList([torch.nn.Linear(width, width), torch.nn.Linear(width, width)])
+                 for _ in range(n_blocks)])
+            self.out = torch.nn.Linear(width, n_out)
+
+        def forward(self, x):
+            x = torch.relu(self.inp(x))
+            for l1, l2 in self.blocks:
+                x = torch.relu(l2(torch.relu(l1(x))) + x)
+            return self.out(x)
+
+        def export(self):
+            layers = [self.inp] + [l for blk in self.blocks for l in blk] + [self.out]
+            return ([l.weight.detach().float().cpu().numpy().copy() for l in layers],
+                    [l.bias.detach().float().cpu().numpy().copy() for l in layers])
+
+    return Net()
+
+
+def _mlp_module(n_out: int, hidden: int):
+    import torch
+
+    class Net(torch.nn.Sequential):
+        def export(self):
+            return ([self[i].weight.detach().float().cpu().numpy().copy() for i in (0, 2, 4)],
+                    [self[i].bias.detach().float().cpu().numpy().copy() for i in (0, 2, 4)])
+
+    return Net(torch.nn.Linear(FEATURES, hidden), torch.nn.ReLU(), torch.nn.Linear(hidden, hidden),
+               torch.nn.ReLU(), torch.nn.Linear(hidden, n_out))
+
+
+def oversample(y: np.ndarray, alpha: int, rng: np.random.Generator) -> np.ndarray:
+    """Indices of the training set: every sample once, plus, for each class with fewer
+    than alpha samples, random repeats of its samples up to alpha (empty classes stay
+    empty)."""
+    idx = [np.arange(len(y))]
+    classes, counts = np.unique(y, return_counts=True)
+    for c, k in zip(classes, counts):
+        if k < alpha:
+            idx.append(rng.choice(np.flatnonzero(y == c), int(alpha - k), replace=True))
+    return np.concatenate(idx)
+
+
+def train_paper(rs: int, rules: np.ndarray, hdr: np.ndarray, *, arch: str = "mlp", hidden: int = 256,
+                n_blocks: int = 6, alpha: int = 1000, beta: float = 0.95, rounds: int = 4,
+                epochs: int = 5, batch: int = 8192, lr: float = 1e-3, seed: int = 0, device="cpu",
+                rule_ids: np.ndarray | None = None, log=None):
+    """The training loop of Sec. 6.2 (epochs per round reduced from the paper's 1000):
+    labels from TSS lookups, alpha oversampling, cross-entropy with Adam, the learning rate
+    multiplied by 0.1 after every fifth of a round's epochs, and after each round alpha x 10
+    unless the accuracy on the (not oversampled) labelled set reaches beta. The model is
+    kept across rounds (reading: the paper regenerates the set, not the model).
+    arch "mlp": the plain 104-bit predictor; "resnet": the paper's residual network.
+    Returns (Ws, bs, info) with info = {"rounds": [{"alpha", "samples", "accuracy"}],
+    "converged": bool}."""
+    import torch
+    if rule_ids is None:
+        rule_ids = T.tang_classify_host(rs, hdr)
+    y = tuple_labels(rs, rules, rule_ids)
+    keep = y >= 0
+    y = y[keep]
+    C = T.tang_ruleset_num_tuples(rs)
+    X = (feature_bits_torch if arch == "mlp" else segments_torch)(hdr[keep], device=device)
+    torch.manual_seed(seed)
+    net = (_mlp_module(C, hidden) if arch == "mlp" else _resnet_module(C, hidden, n_blocks)).to(device)
+    yt = torch.as_tensor(y, device=device)
+    rng = np.random.default_rng(seed)
+    info = {"rounds": [], "converged": False}
+    for _ in range(rounds):
+        idx = oversample(y, alpha, rng)
+        opt = torch.optim.Adam(net.parameters(), lr=lr)
+        sched = torch.optim.lr_scheduler.StepLR(opt, step_size=max(1, epochs // 5), gamma=0.1)
+        for _ in range(epochs):
+            perm = torch.as_tensor(rng.permutation(idx), device=device)
+            for s in range(0, len(perm), batch):
+                b = perm[s:s + batch]
+                loss = torch.nn.functional.cross_entropy(net(X[b]), yt[b])
+                opt.zero_grad()
+                loss.backward()
+                opt.step()
+            sched.step()
+        with torch.no_grad():
+            pred = torch.cat([net(X[s:s + 65536]).argmax(1) for s in range(0, len(y), 65536)])
+            acc = float((pred == yt).float().mean())
+        info["rounds"].append({"alpha": int(alpha), "samples": int(len(idx)), "accuracy": acc})
+        if log:
+            log(f"[train] round {len(info['rounds'])}: alpha {alpha}, {len(idx)} samples, accuracy {acc:.4f}")
+        if acc >= beta:
+            info["converged"] = True
+            break
+        alpha *= 10
+    Ws, bs = net.export()
+    return Ws, bs, info
 
 
 def tuple_labels(rs: int, rules: np.ndarray, rule_ids: np.ndarray) -> np.ndarray:
