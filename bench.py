@@ -76,9 +76,10 @@ def main():
                     help="skip the paper-size residual predictor (7 -> 512 -> 6 blocks -> C)")
     ap.add_argument("--skip-configs", action="store_true",
                     help="skip the 1k / 64k configurations and the 80%%-rule-sampled 512k run")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "c6"],
                     help="c3: 512k rules / 16M headers (the headline line); c4: the update "
-                         "stream on the 512k ruleset; c5: the serving loop over three rulesets")
+                         "stream on the 512k ruleset; c5: the serving loop over three rulesets; "
+                         "c6: drifting updates with and without the deferred update")
     ap.add_argument("--rounds", type=int, default=100, help="c4: update rounds")
     ap.add_argument("--requests", type=int, default=2000, help="c5: requests per load level")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -103,6 +104,8 @@ def main():
         return bench_updates(args)
     if args.workload == "c5":
         return bench_serving(args)
+    if args.workload == "c6":
+        return bench_drift(args)
     if args.copy_bytes:
         a = torch.empty(args.copy_bytes // 4, dtype=torch.int32, device=dev).fill_(1)
         b = torch.empty_like(a)
@@ -514,6 +517,88 @@ def bench_resnet(args, rs, d_hdr, d_out, want, C):
     log(f"[bench] residual predictor (6 x 512): predict {res['predict_mpps']:.0f} Mpps "
         f"({tflops:.0f} TFLOP/s), classify {res['classify_mpps']:.0f} Mpps, answers equal: {ok}")
     return res
+
+
+def bench_drift(args):
+    """c6: the paper's dynamic experiment (Sec. 7.4) on one GPU. 65,536 rules; 10 windows,
+    each deleting 2,000 live rules and inserting 2,000 with a SIP prefix length (4) the
+    tuple set lacks (restricted insertion puts them in coarser tuples), then classifying 1M headers
+    drawn from the live rules (BF16 predictor). Run twice on the same stream: immediate
+    updates only, and with the deferred update (tau 5%; theta 2,500 coarse rules, the
+    paper's 10,000 per 256k rules scaled): incremental training fine-tunes the model on
+    fresh labels, full retraining rebuilds the tuple space from the exported live rules.
+    Per window: Mpps, probes per header, the action taken; answers on a seeded sample
+    against the oracle's scan of the live rules."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as orc
+    from paper_2601_03187_amd import synth, train
+    from paper_2601_03187_amd import tang as T
+    from paper_2601_03187_amd.deferred import DeferredUpdate
+
+    cfg = synth.CONFIGS["c6_drift"]
+    rules0 = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering="specificity")
+    stream = synth.make_update_stream(rules0, cfg["windows"], cfg["per_window"], seed=cfg["seed"] + 1,
+                                      prio_range=len(rules0), sip_lengths=cfg["sip_lengths"])
+    n = cfg["n_pkts"]
+    d_out = torch.empty(n, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream()
+
+    def train_on(rs, live, seed, init=None, epochs=4):
+        h = synth.make_packets(live, 1 << 19, seed=seed, frac_in=cfg["frac_in"])
+        Ws, bs, info = train.train_paper(rs, live, h, hidden=cfg["hidden"], alpha=1000, beta=0.0,
+                                         rounds=1, epochs=epochs, device="cuda", init=init)
+        T.tang_model_load(rs, Ws, bs, "bf16", topk=1)
+        return Ws, bs
+
+    res = {}
+    for mode in ("immediate_only", "with_deferred"):
+        rs = T.tang_ruleset_create(0, rules0)
+        model = train_on(rs, rules0, cfg["seed"] + 2, epochs=8)
+        pol = DeferredUpdate(tau=0.05, theta=2_500)
+        rows, mism = [], 0
+        for w in range(cfg["windows"] + 1):
+            if w > 0:
+                ins, dels = stream[w - 1]
+                T.tang_delete(rs, dels)
+                T.tang_insert(rs, ins)
+            live = T.tang_ruleset_export(rs)
+            hdr = synth.make_packets(live, n, seed=cfg["seed"] + 100 + w, frac_in=cfg["frac_in"])
+            d_hdr = torch.from_numpy(hdr.view(np.uint8).reshape(-1)).cuda()
+            st = T.tang_classify(rs, d_hdr, d_out, n, s, want_stats=True)
+            got = d_out.cpu().numpy().view(np.uint32)
+            samp = np.random.default_rng(w).choice(n, 2000, replace=False)
+            mism += int((got[samp] != orc.classify(live, hdr[samp])).sum())
+            ms = time_classify(T, rs, d_hdr, d_out, n, 10)
+            mpps = n / ms / 1e3
+            coarse = T.tang_ruleset_coarse_rules(rs)
+            action = pol.observe(mpps, coarse) if mode == "with_deferred" else None
+            if action == "incremental":
+                model = train_on(rs, live, cfg["seed"] + 200 + w, init=model, epochs=2)
+            elif action == "full":
+                T.tang_ruleset_destroy(rs)
+                rs = T.tang_ruleset_create(0, live)
+                model = train_on(rs, live, cfg["seed"] + 300 + w, epochs=8)
+            if action:
+                pol.deployed(action)
+            rows.append({"window": w, "mpps": mpps, "probes_per_pkt": st["probes"] / n,
+                         "records_per_pkt": st["records"] / n,
+                         "fallback_rate": st["fallbacks"] / n, "coarse_rules": coarse,
+                         "action": action})
+            log(f"[bench c6] {mode} window {w}: {mpps:.0f} Mpps, probes/pkt {st['probes'] / n:.2f}, "
+                f"records/pkt {st['records'] / n:.2f}, coarse rules {coarse}, action {action}")
+            del d_hdr
+        T.tang_ruleset_destroy(rs)
+        res[mode] = {"windows": rows, "sample_mismatches": mism}
+    line = {"metric": "c6 drifting updates: Mpps per window (1 MI355X)",
+            "value": float(np.mean([r["mpps"] for r in res["with_deferred"]["windows"]])),
+            "unit": "Mpps (mean over windows, with deferred update)", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": "c6_drift: 65,536 rules, 10 windows x (2,000 deletes + 2,000 "
+                                   "inserts with SIP prefix length 4), 1M headers per window"},
+            "modes": res}
+    print(json.dumps(line), flush=True)
 
 
 def bench_updates(args):

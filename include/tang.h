@@ -144,6 +144,21 @@ int tang_ruleset_set_stream(tang_ruleset_t* rs, void* stream);
  * biases stay FP32 in every precision. act_scales must be NULL unless precision is FP8.
  * Replaces any previously loaded model. Without a model, classify probes all tuples.
  */
+/*
+ * Drift of the tuple space under updates (Sec. 5.2.2): the number of live rules that an
+ * insert placed in a tuple coarser than their own (SIP, DIP) length signature (restricted
+ * insertion, Sec. 5.2.1), counted since the ruleset was built; a delete of such a rule
+ * lowers it. The deferred-update policy compares it with its threshold theta.
+ */
+int tang_ruleset_coarse_rules(const tang_ruleset_t* rs, size_t* count);
+/*
+ * The live rules, normalised (host bits below each prefix cleared), in ascending
+ * (priority, id) order: what a full rebuild of the tuple space starts from (Sec. 5.2.2).
+ * out == NULL: only *n = number of live rules. Otherwise out (host) must hold cap >= *n
+ * rules, else EINVAL.
+ */
+int tang_ruleset_export(const tang_ruleset_t* rs, tang_rule_t* out, size_t cap, size_t* n);
+
 int tang_model_load(tang_ruleset_t* rs, const tang_mlp_desc_t* desc, const float* const* W,
                     const float* const* b, tang_precision_t precision, const float* act_scales);
 int tang_model_unload(tang_ruleset_t* rs);

@@ -138,6 +138,30 @@ int tang_ruleset_conflict_mask(tang_ruleset_t* rs, uint32_t id, uint32_t* mask) 
     TANG_GUARD_END
 }
 
+int tang_ruleset_coarse_rules(const tang_ruleset_t* rs, size_t* count) {
+    if (!rs || !count) return fail(TANG_EINVAL, "NULL argument");
+    *count = rs->n_coarse;
+    return TANG_OK;
+}
+
+int tang_ruleset_export(const tang_ruleset_t* rs, tang_rule_t* out, size_t cap, size_t* n) {
+    TANG_GUARD_BEGIN
+    if (!rs || !n) return fail(TANG_EINVAL, "NULL argument");
+    *n = rs->n_live;
+    if (!out) return TANG_OK;
+    if (cap < rs->n_live) return fail(TANG_EINVAL, "export buffer holds fewer than the live rules");
+    std::vector<const tang_rule_t*> live;
+    live.reserve(rs->n_live);
+    for (const auto& hr : rs->rules)
+        if (hr.live) live.push_back(&hr.r);
+    std::sort(live.begin(), live.end(), [](const tang_rule_t* a, const tang_rule_t* b) {
+        return a->priority < b->priority || (a->priority == b->priority && a->id < b->id);
+    });
+    for (size_t i = 0; i < live.size(); ++i) out[i] = *live[i];
+    return TANG_OK;
+    TANG_GUARD_END
+}
+
 int tang_ruleset_device_bytes(const tang_ruleset_t* rs, size_t* bytes) {
     if (!rs || !bytes) return fail(TANG_EINVAL, "NULL argument");
     *bytes = rs->device_bytes();

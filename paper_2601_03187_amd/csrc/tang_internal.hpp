@@ -202,6 +202,7 @@ struct tang_ruleset_s {
     std::vector<HRule> rules;                      // handle-indexed, never shrinks
     std::unordered_map<uint32_t, uint32_t> id2h;   // live id -> handle
     size_t n_live = 0;
+    size_t n_coarse = 0;   // live rules held by a tuple coarser than their own signature
     std::vector<std::pair<uint8_t, uint8_t>> sigs; // tuple signatures
     std::vector<uint64_t> tuple_best;              // lower bound on keys per tuple
     std::vector<Bucket> buckets;

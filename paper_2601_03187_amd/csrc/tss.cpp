@@ -493,6 +493,7 @@ int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
         rs->rules.push_back({r, (uint32_t)t, 0, 0, true});
         rs->id2h[r.id] = h;
         rs->n_live++;
+        if (rs->sigs[t] != std::make_pair(r.sip_len, r.dip_len)) rs->n_coarse++;
         rs->tuple_best[t] = std::min(rs->tuple_best[t], key_of(r));
         tang_ruleset_s::BKey k{(uint32_t)t, r.sip & pmask(rs->sigs[t].first),
                                r.dip & pmask(rs->sigs[t].second)};
@@ -550,6 +551,7 @@ int apply_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n) {
         hr.live = false;
         rs->id2h.erase(ids[i]);
         rs->n_live--;
+        if (rs->sigs[hr.tuple] != std::make_pair(hr.r.sip_len, hr.r.dip_len)) rs->n_coarse--;
         if (!mark[hr.bucket]) { mark[hr.bucket] = 1; dirty.push_back(hr.bucket); }
     }
     return flush(rs, dirty, {}, false, false);

@@ -184,10 +184,12 @@ def make_packets(rules: np.ndarray, n: int, seed: int, frac_in: float,
 
 
 def make_update_stream(rules: np.ndarray, rounds: int, per_round: int, seed: int,
-                       prio_range: int | None = None):
+                       prio_range: int | None = None, sip_lengths=None):
     """Interleaved update rounds: each round is (inserts, delete_ids). Inserted rules come
     from the same field generator, priority uniform in [0, prio_range), fresh ids from
-    max(id)+1 upward; deletes are uniform among the ids live at that point."""
+    max(id)+1 upward; deletes are uniform among the ids live at that point. With
+    `sip_lengths`, the inserted rules' SIP prefix lengths are drawn uniformly from it
+    instead (a drifting rule distribution) and their SIPs masked to those lengths."""
     rng = _rng(seed)
     live = list(int(i) for i in rules["id"])
     next_id = int(rules["id"].max()) + 1 if len(rules) else 0
@@ -196,6 +198,11 @@ def make_update_stream(rules: np.ndarray, rounds: int, per_round: int, seed: int
     out = []
     for rd in range(rounds):
         ins = make_rules(per_round, seed=int(rng.integers(0, 2**62)), ordering="literal")
+        if sip_lengths is not None:
+            ln = rng.choice(np.asarray(sip_lengths), size=per_round).astype(np.uint8)
+            mask = np.where(ln == 0, 0, (0xFFFFFFFF << (32 - ln.astype(np.uint64))) & 0xFFFFFFFF)
+            ins["sip_len"] = ln
+            ins["sip"] = (ins["sip"].astype(np.uint64) & mask).astype(np.uint32)
         ins["priority"] = rng.integers(0, prio_range, size=per_round).astype(np.uint32)
         ins["id"] = np.arange(next_id, next_id + per_round, dtype=np.uint32)
         next_id += per_round
@@ -232,4 +239,9 @@ CONFIGS = {
     "c4_512k_updates": dict(n_rules=524_288, n_pkts=1_000_000, frac_in=0.80, zipf=None,
                             mix=0.0, hidden=256, seed=404, rounds=100, per_round=100),
     "c5_serving": dict(sizes=(10_000, 100_000, 524_288), frac_in=0.80, hidden=256, seed=505),
+    # the paper's dynamic experiment (Sec. 7.4) scaled to one GPU: windows of deletes and
+    # inserts with a SIP prefix length the tuple set does not have (a drifting
+    # distribution; one new length keeps a rebuilt tuple space within 32 tuples)
+    "c6_drift": dict(n_rules=65_536, windows=10, per_window=2_000, n_pkts=1_000_000,
+                     frac_in=0.80, hidden=256, seed=606, sip_lengths=(4,)),
 }

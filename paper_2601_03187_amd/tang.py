@@ -84,6 +84,8 @@ _sigs = {
     "tang_ruleset_set_stream": (ctypes.c_int, [_P, _P]),
     "tang_model_load": (ctypes.c_int, [_P, ctypes.POINTER(tang_mlp_desc_t), _P, _P, ctypes.c_int, _P]),
     "tang_model_load_resnet": (ctypes.c_int, [_P, ctypes.POINTER(tang_resnet_desc_t), _P, _P, ctypes.c_int]),
+    "tang_ruleset_coarse_rules": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "tang_ruleset_export": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "tang_model_unload": (ctypes.c_int, [_P]),
     "tang_classify": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, _P, ctypes.POINTER(tang_stats_t)]),
     "tang_predict": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, _P]),
@@ -212,6 +214,22 @@ def tang_model_load(rs: int, Ws, bs, precision="fp32", topk: int = 1, act_scales
         sc = np.ascontiguousarray(np.asarray(act_scales, dtype=np.float32))
     _check(_lib.tang_model_load(rs, ctypes.byref(d), ctypes.cast(wp, _P), ctypes.cast(bp, _P), p,
                                 sc.ctypes.data if sc is not None else None))
+
+
+def tang_ruleset_coarse_rules(rs: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib.tang_ruleset_coarse_rules(rs, ctypes.byref(n)))
+    return int(n.value)
+
+
+def tang_ruleset_export(rs: int) -> np.ndarray:
+    """Live rules (RULE_DTYPE), normalised, in ascending (priority, id) order."""
+    n = ctypes.c_size_t(0)
+    _check(_lib.tang_ruleset_export(rs, None, 0, ctypes.byref(n)))
+    out = np.zeros(int(n.value), dtype=RULE_DTYPE)
+    if len(out):
+        _check(_lib.tang_ruleset_export(rs, out.ctypes.data, len(out), ctypes.byref(n)))
+    return out
 
 
 def tang_model_load_resnet(rs: int, Ws, bs, precision="bf16", topk: int = 1) -> None:

@@ -67,10 +67,12 @@ def _resnet_module(n_out: int, width: int, n_blocks: int):
                 x = torch.relu(l2(torch.relu(l1(x))) + x)
             return self.out(x)
 
+        def layers(self):
+            return [self.inp] + [l for blk in self.blocks for l in blk] + [self.out]
+
         def export(self):
-            layers = [self.inp] + [l for blk in self.blocks for l in blk] + [self.out]
-            return ([l.weight.detach().float().cpu().numpy().copy() for l in layers],
-                    [l.bias.detach().float().cpu().numpy().copy() for l in layers])
+            return ([l.weight.detach().float().cpu().numpy().copy() for l in self.layers()],
+                    [l.bias.detach().float().cpu().numpy().copy() for l in self.layers()])
 
     return Net()
 
@@ -79,9 +81,12 @@ def _mlp_module(n_out: int, hidden: int):
     import torch
 
     class Net(torch.nn.Sequential):
+        def layers(self):
+            return [self[i] for i in (0, 2, 4)]
+
         def export(self):
-            return ([self[i].weight.detach().float().cpu().numpy().copy() for i in (0, 2, 4)],
-                    [self[i].bias.detach().float().cpu().numpy().copy() for i in (0, 2, 4)])
+            return ([l.weight.detach().float().cpu().numpy().copy() for l in self.layers()],
+                    [l.bias.detach().float().cpu().numpy().copy() for l in self.layers()])
 
     return Net(torch.nn.Linear(FEATURES, hidden), torch.nn.ReLU(), torch.nn.Linear(hidden, hidden),
                torch.nn.ReLU(), torch.nn.Linear(hidden, n_out))
@@ -102,13 +107,14 @@ def oversample(y: np.ndarray, alpha: int, rng: np.random.Generator) -> np.ndarra
 def train_paper(rs: int, rules: np.ndarray, hdr: np.ndarray, *, arch: str = "mlp", hidden: int = 256,
                 n_blocks: int = 6, alpha: int = 1000, beta: float = 0.95, rounds: int = 4,
                 epochs: int = 5, batch: int = 8192, lr: float = 1e-3, seed: int = 0, device="cpu",
-                rule_ids: np.ndarray | None = None, log=None):
+                rule_ids: np.ndarray | None = None, init=None, log=None):
     """The training loop of Sec. 6.2 (epochs per round reduced from the paper's 1000):
     labels from TSS lookups, alpha oversampling, cross-entropy with Adam, the learning rate
     multiplied by 0.1 after every fifth of a round's epochs, and after each round alpha x 10
     unless the accuracy on the (not oversampled) labelled set reaches beta. The model is
     kept across rounds (reading: the paper regenerates the set, not the model).
     arch "mlp": the plain 104-bit predictor; "resnet": the paper's residual network.
+    init = (Ws, bs) starts from existing weights (the incremental training of Sec. 5.2.2).
     Returns (Ws, bs, info) with info = {"rounds": [{"alpha", "samples", "accuracy"}],
     "converged": bool}."""
     import torch
@@ -121,6 +127,11 @@ def train_paper(rs: int, rules: np.ndarray, hdr: np.ndarray, *, arch: str = "mlp
     X = (feature_bits_torch if arch == "mlp" else segments_torch)(hdr[keep], device=device)
     torch.manual_seed(seed)
     net = (_mlp_module(C, hidden) if arch == "mlp" else _resnet_module(C, hidden, n_blocks)).to(device)
+    if init is not None:
+        with torch.no_grad():
+            for layer, W, b in zip(net.layers(), init[0], init[1]):
+                layer.weight.copy_(torch.as_tensor(W))
+                layer.bias.copy_(torch.as_tensor(b))
     yt = torch.as_tensor(y, device=device)
     rng = np.random.default_rng(seed)
     info = {"rounds": [], "converged": False}

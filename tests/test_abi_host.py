@@ -163,3 +163,45 @@ def test_empty_ruleset_and_too_many_signatures():
     with pytest.raises(T.TangError) as e:
         T.tang_ruleset_create(T.TANG_HOST_ONLY, r)
     assert e.value.name == "EINVAL"
+
+
+def test_coarse_rule_counter_follows_restricted_insertion(golden_tab_rules):
+    """Sec. 5.2.1 / 5.2.2: R10 (lengths (3,1)) goes to T3 (3,0), a coarser tuple, and
+    counts; R9 (3,3) has its own tuple T1 and does not; deleting R10 takes it back out."""
+    g = golden_tab_rules
+    rs = T.tang_ruleset_create(T.TANG_HOST_ONLY, g["array"])
+    try:
+        assert T.tang_ruleset_coarse_rules(rs) == 0
+        ins = {name: (prio, x, y) for (name, prio, x, y, _) in g["inserts"]}
+        T.tang_insert(rs, np.array([_golden.make_rule("R9", *ins["R9"])], dtype=synth.RULE_DTYPE))
+        assert T.tang_ruleset_coarse_rules(rs) == 0
+        T.tang_insert(rs, np.array([_golden.make_rule("R10", *ins["R10"])], dtype=synth.RULE_DTYPE))
+        assert T.tang_ruleset_coarse_rules(rs) == 1
+        T.tang_delete(rs, [10])
+        assert T.tang_ruleset_coarse_rules(rs) == 0
+    finally:
+        T.tang_ruleset_destroy(rs)
+
+
+def test_export_returns_live_rules_in_priority_order():
+    rules = synth.make_rules(500, seed=23, ordering="literal")
+    rng = np.random.default_rng(1)
+    rs = T.tang_ruleset_create(T.TANG_HOST_ONLY, rules[rng.permutation(len(rules))])
+    try:
+        extra = synth.make_rules(20, seed=24)
+        extra["id"] += 10_000
+        extra["priority"] = rng.integers(0, 500, 20)
+        T.tang_insert(rs, extra)
+        gone = rules["id"][::7]
+        T.tang_delete(rs, gone)
+        got = T.tang_ruleset_export(rs)
+        live = np.concatenate([rules[~np.isin(rules["id"], gone)], extra])
+        order = np.lexsort((live["id"], live["priority"]))
+        assert len(got) == T.tang_ruleset_num_rules(rs) == len(live)
+        assert np.array_equal(got, live[order])
+        # a rebuild from the export has the same answers (same rules, same priorities)
+        rs2 = T.tang_ruleset_create(T.TANG_HOST_ONLY, got)
+        assert T.tang_ruleset_num_rules(rs2) == len(live)
+        T.tang_ruleset_destroy(rs2)
+    finally:
+        T.tang_ruleset_destroy(rs)
