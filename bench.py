@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-literal", action="store_true")
     ap.add_argument("--skip-probe-all", action="store_true")
+    ap.add_argument("--skip-hybrid", action="store_true",
+                    help="skip the paper's CPU-GPU split (GPU predicts, host threads search)")
     ap.add_argument("--skip-stats", action="store_true",
                     help="skip the paper's training loop and its statistics (model accuracy, "
                          "classification accuracy of the paper's own search, memory accesses)")
@@ -251,6 +253,11 @@ def main():
         T.tang_model_load(rs, Ws, bs, base, topk=1, act_scales=sc if base == "fp8" else None)
         configs = other_configs(args, rules, rs, d_hdr, base)
 
+    hybrid = None
+    if not args.skip_hybrid:
+        T.tang_model_load(rs, Ws, bs, "bf16", topk=1)
+        hybrid = bench_hybrid(rs, hdr, d_hdr, got_by_prec[base])
+
     stats = None
     if not args.skip_stats:
         stats = paper_statistics(args, rules, rs, hdr, d_hdr, d_out, got_by_prec[base], C)
@@ -316,7 +323,7 @@ def main():
         "roofline": roof, "kernels": other,
         "per_precision": per, "candidate_change_vs_fp32": cand_change,
         "literal_ordering": lit, "no_model_probe_all": probe_all, "other_configs": configs,
-        "paper_resnet_predictor": resnet, "paper_statistics": stats,
+        "paper_resnet_predictor": resnet, "paper_statistics": stats, "paper_cpu_gpu_split": hybrid,
         "build_s": build_s, "train_top1": acc,
         "cpu_baseline": cpu,
         "paper_context": "TaNG reports 10.98 Mpps average at 512k rules (12 ClassBench-ng rulesets, "
@@ -412,6 +419,52 @@ def other_configs(args, rules3, rs3, d_hdr3, prec3):
                                    "oracle_checked": int(len(samp)),
                                    "mismatches": int((got[samp] != want).sum())}
     log(f"[bench] c3 with 80% rule-sampled headers: {res['c3_512k_80pct_inside']['mpps']:.0f} Mpps")
+    return res
+
+
+def bench_hybrid(rs, hdr, d_hdr, want):
+    """The paper's own split (Sec. 5.1.2) as a comparison: the GPU predicts (BF16 model)
+    chunk k + 1 and copies its candidates to pinned host memory while host threads run the
+    search of chunk k (tang_search_host), on the first 4,194,304 headers of the 512k
+    workload; the paper's search (a lower-priority match in the predicted tuple is kept)
+    and the exact one (ordered search always). Mpps over the whole pipeline, and the share
+    of answers equal to the exact ones."""
+    import concurrent.futures as cf
+
+    import numpy as np
+    import torch
+
+    from oracle import oracle as orc
+    from paper_2601_03187_amd import tang as T
+
+    n, chunk = 1 << 22, 1 << 20
+    threads = orc.default_threads()
+    s = torch.cuda.current_stream()
+    d_cand = torch.empty(n, dtype=torch.int32, device="cuda")
+    h_cand = torch.empty(n, dtype=torch.int32, pin_memory=True)
+    out = np.empty(n, dtype=np.uint32)
+    res = {"headers": n, "chunk": chunk, "host_threads": threads}
+    with cf.ThreadPoolExecutor(1) as ex:
+        for mode, exact in (("paper_search", False), ("exact_search", True)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pend = None
+            for base in range(0, n, chunk):
+                T.tang_predict(rs, d_hdr[16 * base:], d_cand[base:], chunk, s)
+                h_cand[base:base + chunk].copy_(d_cand[base:base + chunk], non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(s)
+                ev.synchronize()
+                if pend is not None:
+                    pend.result()
+                cv = h_cand[base:base + chunk].numpy().view(np.uint32)
+                pend = ex.submit(T.tang_search_host, rs, hdr[base:base + chunk], cv, 1, threads, exact,
+                                 out[base:base + chunk])
+            pend.result()
+            el = time.perf_counter() - t0
+            res[mode] = {"mpps": n / el / 1e6, "agree_with_exact": float(np.mean(out == want[:n]))}
+            log(f"[bench] CPU-GPU split, {mode}: {res[mode]['mpps']:.1f} Mpps on {threads} host threads, "
+                f"answers equal to the exact ones: {res[mode]['agree_with_exact']:.5f}")
     return res
 
 

@@ -203,6 +203,21 @@ int tang_model_load_resnet(tang_ruleset_t* rs, const tang_resnet_desc_t* desc,
  */
 int tang_classify(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id,
                   size_t n, void* stream, tang_stats_t* stats);
+/*
+ * The paper's own split as a comparison mode (Sec. 5.1.2: the GPU predicts, the CPU
+ * searches): the search stage on the host tuple space, `threads` host threads. hdr,
+ * rule_id: host arrays of n; cand: host array of n candidate words as tang_predict
+ * writes them (candidate k in byte k), kcand of them per word (0: no prediction, the
+ * ordered search over all tuples). exact = 0: the paper's search -- the best match of
+ * the predicted tuples if any, else the ordered search over the remaining tuples by best
+ * key (Sec. 5.1.1), so a lower-priority rule can be returned; exact != 0: the ordered
+ * search always runs after the candidates, and the answer equals tang_classify's. Works
+ * on host-only rulesets; must not overlap an update of the ruleset. Synchronous.
+ * stats (optional): packets, probes, records, top1_hits, fallbacks, no_match.
+ */
+int tang_search_host(const tang_ruleset_t* rs, const tang_header_t* hdr, const uint32_t* cand,
+                     uint32_t* rule_id, size_t n, uint32_t kcand, uint32_t threads, int exact,
+                     tang_stats_t* stats);
 /* Same with host pointers; copies in and out and synchronises. For tests and tools. */
 int tang_classify_host(tang_ruleset_t* rs, const tang_header_t* hdr, uint32_t* rule_id,
                        size_t n, tang_stats_t* stats);

@@ -338,6 +338,19 @@ int tang_search(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_io, 
     TANG_GUARD_END
 }
 
+int tang_search_host(const tang_ruleset_t* rs, const tang_header_t* hdr, const uint32_t* cand,
+                     uint32_t* rule_id, size_t n, uint32_t kcand, uint32_t threads, int exact,
+                     tang_stats_t* stats) {
+    TANG_GUARD_BEGIN
+    if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    if (kcand > TANG_MAX_TOPK) return fail(TANG_EINVAL, "kcand must be in 0..4");
+    if (n && (!hdr || !rule_id || (kcand && !cand))) return fail(TANG_EINVAL, "NULL buffer");
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (n == 0) return TANG_OK;
+    return search_host(rs, hdr, cand, rule_id, n, kcand, threads, exact != 0, stats);
+    TANG_GUARD_END
+}
+
 int tang_classify_host(tang_ruleset_t* rs, const tang_header_t* hdr, uint32_t* rule_id, size_t n,
                        tang_stats_t* stats) {
     TANG_GUARD_BEGIN

@@ -274,6 +274,9 @@ int classify_async(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_r
 hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
                       uint32_t* d_cand_packed, float* d_logits, uint8_t* d_cand8,
                       hipStream_t s);
+int search_host(const tang_ruleset_t* rs, const tang_header_t* hdr, const uint32_t* cand,
+                uint32_t* out, size_t n, uint32_t kcand, uint32_t threads, bool exact,
+                tang_stats_t* stats);
 int resnet_prepare(tang_ruleset_t* rs, const tang_resnet_desc_t* d, const float* const* W,
                    const float* const* b, tang_precision_t p);
 hipError_t launch_resnet(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,

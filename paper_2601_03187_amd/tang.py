@@ -85,6 +85,8 @@ _sigs = {
     "tang_model_load": (ctypes.c_int, [_P, ctypes.POINTER(tang_mlp_desc_t), _P, _P, ctypes.c_int, _P]),
     "tang_model_load_resnet": (ctypes.c_int, [_P, ctypes.POINTER(tang_resnet_desc_t), _P, _P, ctypes.c_int]),
     "tang_ruleset_coarse_rules": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "tang_search_host": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, ctypes.c_uint32,
+                                        ctypes.c_uint32, ctypes.c_int, ctypes.POINTER(tang_stats_t)]),
     "tang_ruleset_export": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "tang_model_unload": (ctypes.c_int, [_P]),
     "tang_classify": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, _P, ctypes.POINTER(tang_stats_t)]),
@@ -214,6 +216,25 @@ def tang_model_load(rs: int, Ws, bs, precision="fp32", topk: int = 1, act_scales
         sc = np.ascontiguousarray(np.asarray(act_scales, dtype=np.float32))
     _check(_lib.tang_model_load(rs, ctypes.byref(d), ctypes.cast(wp, _P), ctypes.cast(bp, _P), p,
                                 sc.ctypes.data if sc is not None else None))
+
+
+def tang_search_host(rs: int, hdr: np.ndarray, cand=None, kcand: int = 0, threads: int = 1,
+                     exact: bool = True, out=None, want_stats: bool = False):
+    """Host search (the paper's CPU side); hdr: HDR_DTYPE array, cand: uint32 candidate
+    words or None. Returns the rule ids (and the stats dict when asked). The call releases
+    the GIL (ctypes), so a Python thread can run it beside GPU work."""
+    hdr = np.ascontiguousarray(hdr)
+    if hdr.dtype != HDR_DTYPE:
+        raise TypeError("headers must use HDR_DTYPE")
+    out = np.empty(len(hdr), dtype=np.uint32) if out is None else out
+    c = None if cand is None else np.ascontiguousarray(cand, dtype=np.uint32)
+    st = tang_stats_t() if want_stats else None
+    _check(_lib.tang_search_host(rs, hdr.ctypes.data if len(hdr) else None,
+                                 c.ctypes.data if c is not None and len(c) else None,
+                                 out.ctypes.data if len(out) else None, len(hdr),
+                                 kcand if c is not None else 0, threads, 1 if exact else 0,
+                                 ctypes.byref(st) if st is not None else None))
+    return (out, st.as_dict()) if want_stats else out
 
 
 def tang_ruleset_coarse_rules(rs: int) -> int:
