@@ -34,7 +34,7 @@ extern "C" {
 
 #define TANG_NO_MATCH 0xFFFFFFFFu /* rule_id when no rule matches (no default rule) */
 #define TANG_HOST_ONLY (-1)       /* device argument: build host structures only */
-#define TANG_MAX_TUPLES 32        /* conflict masks are 32-bit */
+#define TANG_MAX_TUPLES 256       /* candidates are bytes; conflict masks up to 8 words */
 #define TANG_MAX_TOPK 4
 #define TANG_MAX_LAYERS 8
 
@@ -80,7 +80,7 @@ typedef enum { TANG_FP32 = 0, TANG_BF16 = 1, TANG_FP8 = 2 } tang_precision_t;
  * layers, dims[0] -> dims[1] -> ... -> dims[n_layers], ReLU after every layer but the
  * last. dims[0] must be 104: the header's bits, most significant first, over SIP(32)
  * DIP(32) SP(16) DP(16) PROTO(8), each as 0.0 or 1.0. dims[n_layers] must equal
- * tang_ruleset_num_tuples(). Supported now: n_layers = 3 with equal hidden widths
+ * tang_ruleset_num_tuples() (1..TANG_MAX_TUPLES). Supported now: n_layers = 3 with equal hidden widths
  * 128 or 256. topk (1..4) is how many top-scoring tuples are probed before
  * certification; equal scores go to the lower tuple index (argmax of Sec. 6.1 for 1).
  */
@@ -127,8 +127,16 @@ int tang_ruleset_tuple(const tang_ruleset_t* rs, uint32_t t, uint8_t* sip_len, u
 size_t tang_ruleset_num_rules(const tang_ruleset_t* rs);
 /* Tuple that holds live rule `id` (ENOTFOUND if none). */
 int tang_ruleset_rule_tuple(const tang_ruleset_t* rs, uint32_t id, uint32_t* tuple);
-/* Conflict mask of live rule `id`, read back from the device (synchronises). */
+/*
+ * Conflict mask of live rule `id` (bit t = tuple t), read back from the device
+ * (synchronises): tang_ruleset_conflict_mask gives tuples 0..31; _words gives n_words
+ * words (word w = tuples 32w..32w+31), zero past the ruleset's mask width. A ruleset built
+ * with at most 32 tuples keeps one mask word per rule (and then cannot grow a 33rd tuple
+ * by insertion: EINVAL); one built with more keeps 8 words (up to 256 tuples).
+ */
 int tang_ruleset_conflict_mask(tang_ruleset_t* rs, uint32_t id, uint32_t* mask);
+int tang_ruleset_conflict_mask_words(tang_ruleset_t* rs, uint32_t id, uint32_t* words,
+                                     uint32_t n_words);
 /* Device bytes held by the ruleset (tables, records, model). */
 int tang_ruleset_device_bytes(const tang_ruleset_t* rs, size_t* bytes);
 /* Stream on which updates are applied (default: the null stream). */

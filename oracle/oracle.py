@@ -388,7 +388,7 @@ def conflict_masks(rules: np.ndarray, tuple_of: np.ndarray) -> np.ndarray:
     """mask[m] = OR of bit tuple_of[r] over rules r with (priority, id) below m's whose
     box intersects m's box (pairwise brute force; small rulesets only)."""
     n = len(rules)
-    out = np.zeros(n, dtype=np.uint64)
+    out = np.zeros(n, dtype=object)  # Python ints: any number of tuples
     keys = [(int(r["priority"]), int(r["id"])) for r in rules]
     for m in range(n):
         acc = 0

@@ -25,7 +25,8 @@ using namespace tang;
 size_t tang_ruleset_s::device_bytes() const {
     if (device == TANG_HOST_ONLY) return 0;
     return slots.size() * sizeof(Slot) + filter.size() * sizeof(uint32_t) +
-           (size_t)rec_cap * sizeof(Rec) + sizeof(TupleTable) +
+           (size_t)rec_cap * sizeof(Rec) + (nw > 1 ? (size_t)rec_cap * kMaskWords * 4 : 0) +
+           sizeof(TupleTable) +
            kStatCopies * sizeof(StatsDev) + model.bytes;
 }
 
@@ -50,6 +51,8 @@ static void free_device(tang_ruleset_t* rs) {
     if (rs->d_filter) hipFree(rs->d_filter);
     rs->d_filter = nullptr;
     if (rs->d_recs) hipFree(rs->d_recs);
+    if (rs->d_cmask) hipFree(rs->d_cmask);
+    rs->d_cmask = nullptr;
     if (rs->d_tt) hipFree(rs->d_tt);
     if (rs->d_stats) hipFree(rs->d_stats);
     for (hipEvent_t e : rs->pipe_events) hipEventDestroy(e);
@@ -123,19 +126,29 @@ int tang_ruleset_rule_tuple(const tang_ruleset_t* rs, uint32_t id, uint32_t* tup
     TANG_GUARD_END
 }
 
-int tang_ruleset_conflict_mask(tang_ruleset_t* rs, uint32_t id, uint32_t* mask) {
+int tang_ruleset_conflict_mask_words(tang_ruleset_t* rs, uint32_t id, uint32_t* words,
+                                     uint32_t n_words) {
     TANG_GUARD_BEGIN
-    if (!rs || !mask) return fail(TANG_EINVAL, "NULL argument");
+    if (!rs || (n_words && !words)) return fail(TANG_EINVAL, "NULL argument");
     if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset has no masks");
     auto it = rs->id2h.find(id);
     if (it == rs->id2h.end()) return fail(TANG_ENOTFOUND, "rule id is not live");
     TANG_HIP(hipSetDevice(rs->device));
+    const uint32_t pos = rs->rules[it->second].pos;
     Rec r;
-    TANG_HIP(hipMemcpy(&r, rs->d_recs + rs->rules[it->second].pos, sizeof r, hipMemcpyDeviceToHost));
+    TANG_HIP(hipMemcpy(&r, rs->d_recs + pos, sizeof r, hipMemcpyDeviceToHost));
     if (r.id != id) return fail(TANG_EINVAL, "record/handle mismatch");
-    *mask = r.cmask;
+    uint32_t row[kMaskWords] = {r.cmask};
+    if (rs->nw > 1)
+        TANG_HIP(hipMemcpy(row, rs->d_cmask + (size_t)pos * kMaskWords, sizeof row, hipMemcpyDeviceToHost));
+    for (uint32_t w = 0; w < n_words; ++w) words[w] = w < kMaskWords ? row[w] : 0u;
     return TANG_OK;
     TANG_GUARD_END
+}
+
+int tang_ruleset_conflict_mask(tang_ruleset_t* rs, uint32_t id, uint32_t* mask) {
+    if (!mask) return fail(TANG_EINVAL, "NULL argument");
+    return tang_ruleset_conflict_mask_words(rs, id, mask, 1);
 }
 
 int tang_ruleset_coarse_rules(const tang_ruleset_t* rs, size_t* count) {

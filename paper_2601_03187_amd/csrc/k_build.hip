@@ -26,42 +26,71 @@ __device__ __forceinline__ BoxDev rec_box(const Rec& r, uint32_t pos) {
                   meta_proto(r.meta) | (meta_exact(r.meta) << 8) | (meta_tuple(r.meta) << 16), pos};
 }
 
+// Mask words of rule at record position p: the record's own word (NW = 1) or a row of
+// the side array.
+template <int NW>
+__device__ __forceinline__ uint32_t* mask_row(Rec* recs, uint32_t* cmask, uint32_t p) {
+    if constexpr (NW == 1) return &recs[p].cmask;
+    else return cmask + (size_t)p * NW;
+}
+
 // One thread per rule i (boxes in ascending key order); rules j < i stream through LDS.
+template <int NW>
 __global__ __launch_bounds__(256) void k_conflict_build(const BoxDev* __restrict__ boxes,
                                                         uint32_t n, Rec* __restrict__ recs,
-                                                        uint32_t all_mask) {
+                                                        uint32_t* __restrict__ cmask,
+                                                        const uint32_t* __restrict__ all_mask) {
     __shared__ BoxDev tile[256];
     const uint32_t base = blockIdx.x * 256u;
     const uint32_t i = base + threadIdx.x;
     const bool valid = i < n;
     BoxDev me = valid ? boxes[i] : BoxDev{0, 0, 0, 0, 0, 0, 0, 0};
-    uint32_t mask = 0;
+    uint32_t mask[NW], full[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        mask[w] = 0;
+        full[w] = all_mask[w];
+    }
+    auto done = [&]() {
+        bool f = true;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) f &= mask[w] == full[w];
+        return f;
+    };
     const uint32_t j_end = min(n, base + 256u);  // block-uniform
     for (uint32_t j0 = 0; j0 < j_end; j0 += 256u) {
-        if (!__syncthreads_or(valid && mask != all_mask)) break;
+        if (!__syncthreads_or(valid && !done())) break;
         const uint32_t j = j0 + threadIdx.x;
         if (j < n) tile[threadIdx.x] = boxes[j];
         __syncthreads();
-        if (valid && mask != all_mask && i > j0) {
+        if (valid && !done() && i > j0) {
             const uint32_t cnt = min(256u, i - j0);
             for (uint32_t k = 0; k < cnt; ++k) {
-                const uint32_t tb = 1u << (tile[k].pt >> 16);
-                if (mask & tb) continue;
-                if (box_meet(me, tile[k])) mask |= tb;
+                const uint32_t t = tile[k].pt >> 16;
+                const uint32_t tb = 1u << (t & 31u);
+                uint32_t& word = mask[NW == 1 ? 0 : t >> 5];
+                if (word & tb) continue;
+                if (box_meet(me, tile[k])) word |= tb;
             }
         }
         __syncthreads();
     }
-    if (valid) recs[me.pos].cmask = mask;
+    if (valid) {
+        uint32_t* row = mask_row<NW>(recs, cmask, me.pos);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) row[w] = mask[w];
+    }
 }
 
 // After inserts: every live record p is compared with each fresh rule q. If they meet,
 // the better-keyed one's tuple goes into the other's mask.
-__global__ __launch_bounds__(256) void k_conflict_update(Rec* __restrict__ recs, uint32_t used,
+template <int NW>
+__global__ __launch_bounds__(256) void k_conflict_update(Rec* __restrict__ recs,
+                                                         uint32_t* __restrict__ cmask, uint32_t used,
                                                          const uint32_t* __restrict__ new_pos,
                                                          uint32_t n_new) {
     __shared__ BoxDev q[256];
-    __shared__ uint32_t qkey_p[256], qkey_i[256], qadd[256];
+    __shared__ uint32_t qkey_p[256], qkey_i[256], qadd[256][NW];
     const uint32_t p = blockIdx.x * 256u + threadIdx.x;
     Rec me;
     bool live = false;
@@ -70,7 +99,10 @@ __global__ __launch_bounds__(256) void k_conflict_update(Rec* __restrict__ recs,
         live = !(me.prio == kDead && me.id == kDead);
     }
     const BoxDev mb = live ? rec_box(me, p) : BoxDev{0, 0, 0, 0, 0, 0, 0, 0};
-    uint32_t add = 0;
+    const uint32_t my_t = meta_tuple(me.meta);
+    uint32_t add[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) add[w] = 0;
     for (uint32_t q0 = 0; q0 < n_new; q0 += 256u) {
         const uint32_t cnt = min(256u, n_new - q0);
         if (threadIdx.x < cnt) {
@@ -79,25 +111,37 @@ __global__ __launch_bounds__(256) void k_conflict_update(Rec* __restrict__ recs,
             q[threadIdx.x] = rec_box(r, pos);
             qkey_p[threadIdx.x] = r.prio;
             qkey_i[threadIdx.x] = r.id;
-            qadd[threadIdx.x] = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) qadd[threadIdx.x][w] = 0;
         }
         __syncthreads();
         if (live) {
             for (uint32_t k = 0; k < cnt; ++k) {
                 if (q[k].pos == p || !box_meet(mb, q[k])) continue;
                 const bool better = me.prio < qkey_p[k] || (me.prio == qkey_p[k] && me.id < qkey_i[k]);
-                if (better)
-                    atomicOr(&qadd[k], 1u << meta_tuple(me.meta));
-                else
-                    add |= 1u << (q[k].pt >> 16);
+                if (better) {
+                    atomicOr(&qadd[k][NW == 1 ? 0 : my_t >> 5], 1u << (my_t & 31u));
+                } else {
+                    const uint32_t t = q[k].pt >> 16;
+                    add[NW == 1 ? 0 : t >> 5] |= 1u << (t & 31u);
+                }
             }
         }
         __syncthreads();
-        if (threadIdx.x < cnt && qadd[threadIdx.x])
-            atomicOr(&recs[q[threadIdx.x].pos].cmask, qadd[threadIdx.x]);
+        if (threadIdx.x < cnt) {
+            uint32_t* row = mask_row<NW>(recs, cmask, q[threadIdx.x].pos);
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+                if (qadd[threadIdx.x][w]) atomicOr(&row[w], qadd[threadIdx.x][w]);
+        }
         __syncthreads();
     }
-    if (live && add) atomicOr(&recs[p].cmask, add);
+    if (live) {
+        uint32_t* row = mask_row<NW>(recs, cmask, p);
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            if (add[w]) atomicOr(&row[w], add[w]);
+    }
 }
 
 __global__ void k_stage_records(const Rec* __restrict__ recs, const Rec* __restrict__ fresh,
@@ -116,6 +160,21 @@ __global__ void k_place_records(Rec* __restrict__ recs, const Rec* __restrict__ 
     recs[dst[i]] = stage[i];
 }
 
+__global__ void k_stage_masks(const uint32_t* __restrict__ cmask, const uint32_t* __restrict__ src,
+                              uint32_t n, uint32_t* __restrict__ stage) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * kMaskWords) return;
+    const uint32_t r = i / kMaskWords, w = i % kMaskWords, s = src[r];
+    stage[i] = (s & 0x80000000u) ? 0u : cmask[(size_t)s * kMaskWords + w];
+}
+
+__global__ void k_place_masks(uint32_t* __restrict__ cmask, const uint32_t* __restrict__ stage,
+                              const uint32_t* __restrict__ dst, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * kMaskWords) return;
+    cmask[(size_t)dst[i / kMaskWords] * kMaskWords + i % kMaskWords] = stage[i];
+}
+
 __global__ void k_scatter_slots(Slot* __restrict__ slots, const uint32_t* __restrict__ idx,
                                 const Slot* __restrict__ val, uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,19 +183,27 @@ __global__ void k_scatter_slots(Slot* __restrict__ slots, const uint32_t* __rest
 
 }  // namespace
 
-hipError_t launch_conflict_build(const BoxDev* d_boxes, size_t n, Rec* d_recs, uint32_t all_mask,
-                                 hipStream_t s) {
+hipError_t launch_conflict_build(const BoxDev* d_boxes, size_t n, Rec* d_recs, uint32_t* d_cmask,
+                                 uint32_t nw, const uint32_t* all_mask, hipStream_t s) {
     if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_conflict_build, dim3((n + 255) / 256), dim3(256), 0, s, d_boxes,
-                       (uint32_t)n, d_recs, all_mask);
+    const dim3 g((n + 255) / 256), b(256);
+    if (nw == 1)
+        hipLaunchKernelGGL(k_conflict_build<1>, g, b, 0, s, d_boxes, (uint32_t)n, d_recs, d_cmask, all_mask);
+    else
+        hipLaunchKernelGGL(k_conflict_build<kMaskWords>, g, b, 0, s, d_boxes, (uint32_t)n, d_recs,
+                           d_cmask, all_mask);
     return hipGetLastError();
 }
 
-hipError_t launch_conflict_update(Rec* d_recs, uint32_t rec_used, const uint32_t* d_new_pos,
-                                  uint32_t n_new, hipStream_t s) {
+hipError_t launch_conflict_update(Rec* d_recs, uint32_t* d_cmask, uint32_t nw, uint32_t rec_used,
+                                  const uint32_t* d_new_pos, uint32_t n_new, hipStream_t s) {
     if (!n_new || !rec_used) return hipSuccess;
-    hipLaunchKernelGGL(k_conflict_update, dim3((rec_used + 255) / 256), dim3(256), 0, s, d_recs,
-                       rec_used, d_new_pos, n_new);
+    const dim3 g((rec_used + 255) / 256), b(256);
+    if (nw == 1)
+        hipLaunchKernelGGL(k_conflict_update<1>, g, b, 0, s, d_recs, d_cmask, rec_used, d_new_pos, n_new);
+    else
+        hipLaunchKernelGGL(k_conflict_update<kMaskWords>, g, b, 0, s, d_recs, d_cmask, rec_used,
+                           d_new_pos, n_new);
     return hipGetLastError();
 }
 
@@ -148,6 +215,17 @@ hipError_t launch_move_records(Rec* d_recs, const Rec* d_fresh, const uint32_t* 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_place_records, g, b, 0, s, d_recs, d_stage, d_dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_move_masks(uint32_t* d_cmask, const uint32_t* d_src, const uint32_t* d_dst,
+                             uint32_t n, uint32_t* d_stage, hipStream_t s) {
+    if (!n) return hipSuccess;
+    const dim3 g((n * kMaskWords + 255) / 256), b(256);
+    hipLaunchKernelGGL(k_stage_masks, g, b, 0, s, d_cmask, d_src, n, d_stage);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_place_masks, g, b, 0, s, d_cmask, d_stage, d_dst, n);
     return hipGetLastError();
 }
 

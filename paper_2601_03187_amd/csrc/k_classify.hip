@@ -19,7 +19,7 @@ namespace tang {
 namespace {
 
 struct Best {
-    uint32_t prio, id, cmask, tuple;
+    uint32_t prio, id, cmask, tuple, pos;   // pos: record index (for wide conflict masks)
 };
 
 __device__ __forceinline__ bool kless(uint32_t p1, uint32_t i1, uint32_t p2, uint32_t i2) {
@@ -48,7 +48,7 @@ __device__ __forceinline__ void scan_list(uint32_t off, uint32_t len, uint32_t s
         if (STATS) ++n_recs;
         if (!kless(r.prio, r.id, b.prio, b.id)) break;
         if (rec_match(r, sip, dip, sp, dp, proto)) {
-            b = Best{r.prio, r.id, r.cmask, meta_tuple(r.meta)};
+            b = Best{r.prio, r.id, r.cmask, meta_tuple(r.meta), off + k};
             break;
         }
     }
@@ -65,7 +65,7 @@ __device__ __forceinline__ Slot find_slot(uint64_t h64, uint32_t tk, uint32_t k0
     for (uint32_t step = 0; step <= slot_mask; ++step) {
         const Slot s = slots[h];
         if (STATS) ++n_slots;
-        if (s.tl == kEmptyTL || (s.ms == k0 && s.md == k1 && (s.tl >> 24) == tk)) return s;
+        if (s.tl == kEmptyTL || (s.ms == k0 && s.md == k1 && (s.tl >> kTlShift) == tk)) return s;
         h = (h + 1) & slot_mask;
     }
     return Slot{0, 0, kEmptyTL, 0};
@@ -92,7 +92,7 @@ __device__ __forceinline__ void search_tuple(uint32_t t, uint64_t h, uint32_t ms
     const uint32_t keys[4][2] = {{kSubDp, dp}, {kSubSp, sp}, {kSubProto, proto}, {kSubRest, 0u}};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const uint32_t tk = t | (keys[q][0] << 5);
+        const uint32_t tk = t | (keys[q][0] << kKindShift);
         const Slot u = find_slot<STATS>(key_hash(tk, bi, keys[q][1]), tk, bi, keys[q][1], slot_mask,
                                         slots, n_slots);
         if (u.tl != kEmptyTL)
@@ -136,38 +136,45 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
-template <bool STATS>
+// NW: conflict-mask words (1 for at most 32 tuples, kMaskWords for up to 256). Tuple
+// sets are NW-word bit masks (word t / 32, bit t % 32); everything else is as for one word.
+template <bool STATS, int NW>
 __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                                                   uint32_t* __restrict__ out, uint32_t n,
                                                   const Slot* __restrict__ slots,
                                                   const Rec* __restrict__ recs,
+                                                  const uint32_t* __restrict__ cmask_rows,
                                                   const uint32_t* __restrict__ filter,
                                                   const TupleTable* __restrict__ ttg, int kcand,
                                                   StatsDev* __restrict__ st) {
-    __shared__ TupleDev s_t[TANG_MAX_TUPLES];
-    __shared__ uint2 s_rank[TANG_MAX_TUPLES];  // best keys in ascending order
-    __shared__ uint32_t s_prefix[TANG_MAX_TUPLES + 1];
+    constexpr uint32_t NT = 32u * NW;
+    __shared__ TupleDev s_t[NT];
+    __shared__ uint2 s_rank[NT];  // best keys in ascending order
+    __shared__ uint32_t s_prefix[NT + 1][NW];
+    __shared__ uint32_t s_all[NW];
     __shared__ uint32_t s_misc[4];
     const int tid = threadIdx.x;
-    if (tid < TANG_MAX_TUPLES) {
-        s_t[tid] = ttg->t[tid];
-        s_rank[tid] = make_uint2(ttg->rank_prio[tid], ttg->rank_id[tid]);
+    for (uint32_t k = tid; k < NT; k += 256u) {
+        s_t[k] = ttg->t[k];
+        s_rank[k] = make_uint2(ttg->rank_prio[k], ttg->rank_id[k]);
     }
-    if (tid <= TANG_MAX_TUPLES) s_prefix[tid] = ttg->prefix[tid];
+    for (uint32_t k = tid; k < (NT + 1) * NW; k += 256u) s_prefix[k / NW][k % NW] = ttg->prefix[k / NW][k % NW];
+    if (tid < NW) s_all[tid] = ttg->all_mask[tid];
     if (tid == 0) {
         s_misc[0] = ttg->n;
-        s_misc[1] = ttg->all_mask;
         s_misc[2] = ttg->slot_mask;
         s_misc[3] = ttg->filter_mask;
     }
     __syncthreads();
-    const uint32_t ntup = s_misc[0], all_mask = s_misc[1], slot_mask = s_misc[2],
-                   filter_mask = s_misc[3];
+    const uint32_t ntup = s_misc[0], slot_mask = s_misc[2], filter_mask = s_misc[3];
     const uint32_t i = blockIdx.x * 256u + tid;
     uint32_t n_probe = 0, n_slots = 0, n_recs = 0, top1 = 0, fb = 0, nm = 0, active = 0;
     uint32_t n_filter = 0, n_steps = 0, n_rounds = 0;
-    uint32_t sip = 0, dip = 0, sp = 0, dp = 0, proto = 0, todo = 0, c0 = 0xFFu;
-    Best b{kDead, kDead, 0u, 0u};
+    uint32_t sip = 0, dip = 0, sp = 0, dp = 0, proto = 0, c0 = 0xFFu;
+    uint32_t todo[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) todo[w] = 0;
+    Best b{kDead, kDead, 0u, 0u, 0u};
     if (i < n) {
         active = 1;
         const uint4 h = hdr[i];
@@ -177,70 +184,102 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
         dp = h.z >> 16;
         proto = h.w & 0xFFu;
         bool found = false;
-        uint32_t probed = 0;
+        uint32_t probed[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) probed[w] = 0;
         if (kcand > 0) {
             const uint32_t cp = out[i];
             for (int c = 0; c < kcand; ++c) {
                 const uint32_t t = (cp >> (8 * c)) & 0xFFu;
                 if (c == 0) c0 = t;
-                if (t >= ntup || ((probed >> t) & 1u)) continue;
-                probed |= 1u << t;
+                if (t >= ntup) continue;
+                uint32_t& pw = probed[NW == 1 ? 0 : t >> 5];
+                if ((pw >> (t & 31u)) & 1u) continue;
+                pw |= 1u << (t & 31u);
                 if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) continue;
                 probe<STATS>(t, sip, dip, sp, dp, proto, s_t, slot_mask, filter_mask, filter, slots,
                              recs, b, n_probe, n_slots, n_recs, n_filter);
             }
             found = b.id != kDead;
         }
-        todo = (found ? b.cmask : all_mask) & ~probed & all_mask;
+        if (NW == 1 || !found) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+                todo[w] = (found ? b.cmask : s_all[w]) & ~probed[w] & s_all[w];
+        } else {
+            const uint4* row = reinterpret_cast<const uint4*>(cmask_rows + (size_t)b.pos * NW);
+#pragma unroll
+            for (int q = 0; q < NW / 4; ++q) {
+                const uint4 m = row[q];
+                todo[4 * q] = m.x & ~probed[4 * q];
+                todo[4 * q + 1] = m.y & ~probed[4 * q + 1];
+                todo[4 * q + 2] = m.z & ~probed[4 * q + 2];
+                todo[4 * q + 3] = m.w & ~probed[4 * q + 3];
+            }
+        }
         if (STATS) fb = found ? 0u : 1u;
     }
     // Certification. First drop the tuples whose best key cannot beat the answer: the
     // tuples in ascending best-key order form a prefix, found by a binary search.
-    if (todo) {
-        uint32_t k = 0;
+    {
+        uint32_t any = 0;
 #pragma unroll
-        for (uint32_t step = 32; step > 0; step >>= 1)
-            if (k + step <= ntup && kless(s_rank[k + step - 1].x, s_rank[k + step - 1].y, b.prio, b.id))
-                k += step;
-        todo &= s_prefix[k];
+        for (int w = 0; w < NW; ++w) any |= todo[w];
+        if (any) {
+            uint32_t k = 0;
+#pragma unroll
+            for (uint32_t step = NT; step > 0; step >>= 1)
+                if (k + step <= ntup && kless(s_rank[k + step - 1].x, s_rank[k + step - 1].y, b.prio, b.id))
+                    k += step;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) todo[w] &= s_prefix[k][w];
+        }
     }
     // Phase 1: the filter bits of every remaining tuple, eight tuples per batch with their
     // loads issued back to back (batches no lane of the wave needs are skipped);
-    // `todo` keeps the tuples whose bit is set.
-    const uint32_t wave_todo = wave_or(todo);
-    uint32_t hits = 0;
-    for (uint32_t t0 = 0; t0 < ntup; t0 += 8) {
-        if (!((wave_todo >> t0) & 0xFFu)) continue;
-        if (STATS) ++n_rounds;
-        uint32_t w[8], pos[8];
+    // `hits` keeps the tuples whose bit is set.
+    uint32_t hits[NW];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t t = t0 + q;
-            w[q] = 0;
-            pos[q] = 0;
-            if ((todo >> t) & 1u) {  // t < ntup: todo holds only existing tuples
-                const uint32_t bit =
-                    filter_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask) & filter_mask;
-                w[q] = filter[bit >> 5];
-                pos[q] = bit & 31u;
-                if (STATS) ++n_filter;
+    for (int w = 0; w < NW; ++w) {
+        hits[w] = 0;
+        const uint32_t wave_todo = wave_or(todo[w]);
+        if (!wave_todo) continue;
+        for (uint32_t t0 = 0; t0 < 32u && 32u * w + t0 < ntup; t0 += 8) {
+            if (!((wave_todo >> t0) & 0xFFu)) continue;
+            if (STATS) ++n_rounds;
+            uint32_t wd[8], pos[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t t = 32u * w + t0 + q;
+                wd[q] = 0;
+                pos[q] = 0;
+                if ((todo[w] >> (t0 + q)) & 1u) {  // t < ntup: todo holds only existing tuples
+                    const uint32_t bit =
+                        filter_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask) & filter_mask;
+                    wd[q] = filter[bit >> 5];
+                    pos[q] = bit & 31u;
+                    if (STATS) ++n_filter;
+                }
             }
-        }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) hits |= ((w[q] >> pos[q]) & 1u) << (t0 + q);
+            for (int q = 0; q < 8; ++q) hits[w] |= ((wd[q] >> pos[q]) & 1u) << (t0 + q);
+        }
     }
     // Phase 2: each lane searches its own passing tuples (so a wave takes as many steps as
     // its busiest lane, not as the union of its lanes' tuples), skipping any whose best key
     // can no longer beat the answer; the order does not matter for the result.
     uint32_t steps = 0;
-    while (hits) {
-        const uint32_t t = __builtin_ctz(hits);
-        hits &= hits - 1u;
-        if (STATS) ++steps;
-        if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) continue;
-        const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
-        search_tuple<STATS>(t, key_hash(t, ms, md), ms, md, sip, dip, sp, dp, proto, slot_mask, slots,
-                            recs, b, n_probe, n_slots, n_recs);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        while (hits[w]) {
+            const uint32_t t = 32u * w + (uint32_t)__builtin_ctz(hits[w]);
+            hits[w] &= hits[w] - 1u;
+            if (STATS) ++steps;
+            if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) continue;
+            const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
+            search_tuple<STATS>(t, key_hash(t, ms, md), ms, md, sip, dip, sp, dp, proto, slot_mask,
+                                slots, recs, b, n_probe, n_slots, n_recs);
+        }
     }
     if (STATS) n_steps = wave_max(steps);
     if (active) {
@@ -281,12 +320,17 @@ hipError_t launch_classify(const tang_ruleset_t* rs, const tang_header_t* d_hdr,
         const uint32_t m = (uint32_t)std::min(chunk, n - base);
         const dim3 grid((m + 255) / 256), block(256);
         const uint4* h = reinterpret_cast<const uint4*>(d_hdr) + base;
-        if (stats)
-            hipLaunchKernelGGL(k_classify<true>, grid, block, 0, s, h, d_out + base, m, rs->d_slots,
-                               rs->d_recs, rs->d_filter, rs->d_tt, kcand, rs->d_stats);
-        else
-            hipLaunchKernelGGL(k_classify<false>, grid, block, 0, s, h, d_out + base, m,
-                               rs->d_slots, rs->d_recs, rs->d_filter, rs->d_tt, kcand, rs->d_stats);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, block, 0, s, h, d_out + base, m, rs->d_slots, rs->d_recs,
+                               rs->d_cmask, rs->d_filter, rs->d_tt, kcand, rs->d_stats);
+        };
+        if (rs->nw == 1) {
+            if (stats) go(k_classify<true, 1>);
+            else go(k_classify<false, 1>);
+        } else {
+            if (stats) go(k_classify<true, kMaskWords>);
+            else go(k_classify<false, kMaskWords>);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -41,6 +41,8 @@ template <> struct FragT<TANG_FP8> { using T = u32x8; static constexpr int KB = 
 struct MlpArgs {
     int n_out;
     int topk;
+    uint32_t n3;      // output-layer fragments stored (2 per K block per 32 classes)
+    uint32_t nbias;   // biases stored: 2 H + 32 x class blocks
     float deq[3];
     float inv_a[3];
     float hs[2];  // FP8 hidden layers: deq[l] * inv_a[l + 1] (product scale into next input)
@@ -217,7 +219,9 @@ __device__ __forceinline__ void epi_hidden(const f4 (&acc)[NT], int mt, const fl
     }
 }
 
-template <int PREC, int H, int NT, int LDSM, int WAVES>
+// OUTB: most blocks of 32 output classes (1, or 8 for up to 256 tuples; the W3 fragments
+// of a multi-block model are read from L2).
+template <int PREC, int H, int NT, int LDSM, int WAVES, int OUTB>
 __global__ __launch_bounds__(64 * WAVES) void k_mlp(
     const uint4* __restrict__ hdr, uint32_t n, const typename FragT<PREC>::T* __restrict__ w1,
     const typename FragT<PREC>::T* __restrict__ w2, const typename FragT<PREC>::T* __restrict__ w3,
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
     // FP32 input blocks past feature 104 are all-zero on both operands: skipped
     constexpr int KBN1_USED = PREC == TANG_FP32 ? 104 / KB : KBN1;
     constexpr uint32_t n1 = MTH * KBN1 * 64, n2 = MTH * KBNH * 64, n3 = 2 * KBNH * 64;
-    constexpr uint32_t nb = 2 * H + kOutPad;
+    static_assert(OUTB == 1 || !(LDSM & 4), "multi-block output layers stay in L2");
     // output tiles per MFMA group in layer 2 (more when each tile is only 1-2 MFMAs)
     constexpr int TG = PREC == TANG_FP8 ? 2 : PREC == TANG_BF16 ? 2 : 1;
 
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
     F* s2 = s1 + ((LDSM & 1) ? n1 : 0);
     F* s3 = s2 + ((LDSM & 2) ? n2 : 0);
     float* sb = reinterpret_cast<float*>(s3 + ((LDSM & 4) ? n3 : 0));
-    unsigned char* stab = reinterpret_cast<unsigned char*>(sb + nb);  // BF16 / FP8 bit table
+    unsigned char* stab = reinterpret_cast<unsigned char*>(sb + 2 * H + kOutPad * OUTB);  // bit table
 
     {   // stage resident weights and the biases
         auto copy16 = [&](void* dst, const void* src, uint32_t bytes) {
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
         if (LDSM & 1) copy16(s1, w1, n1 * sizeof(F));
         if (LDSM & 2) copy16(s2, w2, n2 * sizeof(F));
         if (LDSM & 4) copy16(s3, w3, n3 * sizeof(F));
-        copy16(sb, bias_g, nb * sizeof(float));
+        copy16(sb, bias_g, a.nbias * sizeof(float));
         if constexpr (PREC != TANG_FP32)
             if (threadIdx.x < 256) Bits<PREC>::entry(threadIdx.x, stab + threadIdx.x * Bits<PREC>::kEntry);
     }
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
 
     const __amdgpu_buffer_rsrc_t r1 = __builtin_amdgcn_make_buffer_rsrc((void*)w1, 0, n1 * sizeof(F), 0x00020000);
     const __amdgpu_buffer_rsrc_t r2 = __builtin_amdgcn_make_buffer_rsrc((void*)w2, 0, n2 * sizeof(F), 0x00020000);
-    const __amdgpu_buffer_rsrc_t r3 = __builtin_amdgcn_make_buffer_rsrc((void*)w3, 0, n3 * sizeof(F), 0x00020000);
+    const __amdgpu_buffer_rsrc_t r3 = __builtin_amdgcn_make_buffer_rsrc((void*)w3, 0, a.n3 * sizeof(F), 0x00020000);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
     const uint32_t tiles = (n + 16 * NT - 1) / (16 * NT);
     const int C = a.n_out;
@@ -348,45 +352,83 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                 epi_hidden<PREC, NT, KBNH>(acc[u], mt0 + u, sb + H, a.hs[1], g, a1);
             __builtin_amdgcn_sched_barrier(0);
         }
-        // layer 3: H -> C (two 16-row tiles)
-        f4 z[2][NT];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) z[mt][nt] = (f4){0, 0, 0, 0};
-#pragma unroll
-            for (int kb = 0; kb < KBNH; ++kb) {
-                const F A = ldf<(LDSM & 4) != 0>(s3, r3, mt * KBNH + kb, lane, sbase);
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt) z[mt][nt] = mma(A, a1[kb][nt], z[mt][nt]);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        // scores, then top-k with ties to the lower tuple index
+        // layer 3: H -> C in blocks of 32 classes (two 16-row tiles). With one block each
+        // lane's 8 scores go straight to the top-k; with more, each lane keeps a running
+        // top-4 of the classes it holds (a strictly larger score displaces, so ties keep
+        // the lower class, as classes ascend block by block).
         const float* sb3 = sb + 2 * H;
+        constexpr int KL = OUTB == 1 ? 8 : 4;
+        float v[NT][KL];
+        int cl[NT][KL];
+        if constexpr (OUTB > 1) {
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const uint32_t pkt = pbase + nt * 16 + col;
-            float v[8];
-            int cl[8];
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int q = 0; q < KL; ++q) {
+                    v[nt][q] = -INFINITY;
+                    cl[nt][q] = 1 << 20;
+                }
+        }
+        const int ncb = OUTB == 1 ? 1 : (C + 31) / 32;
+#pragma unroll 1
+        for (int cb = 0; cb < ncb; ++cb) {
+            f4 z[2][NT];
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int c = 16 * mt + 4 * g + r;
-                    float val = (PREC == TANG_FP8 ? z[mt][nt][r] * a.deq[2] : z[mt][nt][r]) + sb3[c];
-                    if (logits && pkt < n && c < C) logits[(size_t)pkt * C + c] = val;
-                    v[4 * mt + r] = (c < C && val == val) ? val : -INFINITY;
-                    cl[4 * mt + r] = c;
+                for (int nt = 0; nt < NT; ++nt) z[mt][nt] = (f4){0, 0, 0, 0};
+#pragma unroll
+                for (int kb = 0; kb < KBNH; ++kb) {
+                    const F A = ldf<(LDSM & 4) != 0>(s3, r3, (2 * cb + mt) * KBNH + kb, lane, sbase);
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) z[mt][nt] = mma(A, a1[kb][nt], z[mt][nt]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // scores
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const uint32_t pkt = pbase + nt * 16 + col;
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int c = 32 * cb + 16 * mt + 4 * g + r;
+                        float val = (PREC == TANG_FP8 ? z[mt][nt][r] * a.deq[2] : z[mt][nt][r]) + sb3[c];
+                        if (logits && pkt < n && c < C) logits[(size_t)pkt * C + c] = val;
+                        float x = (c < C && val == val) ? val : -INFINITY;
+                        if constexpr (OUTB == 1) {
+                            v[nt][4 * mt + r] = x;
+                            cl[nt][4 * mt + r] = c;
+                        } else {
+                            int xc = c;
+#pragma unroll
+                            for (int q = 0; q < KL; ++q) {
+                                if (x > v[nt][q]) {
+                                    const float tv = v[nt][q];
+                                    const int tc = cl[nt][q];
+                                    v[nt][q] = x;
+                                    cl[nt][q] = xc;
+                                    x = tv;
+                                    xc = tc;
+                                }
+                            }
+                        }
+                    }
                 }
             }
+        }
+        // top-k with ties to the lower tuple index
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const uint32_t pkt = pbase + nt * 16 + col;
             uint32_t packed = 0;
             for (int k = 0; k < a.topk; ++k) {
-                float bv = v[0];
-                int bc = cl[0];
+                float bv = v[nt][0];
+                int bc = cl[nt][0];
 #pragma unroll
-                for (int q = 1; q < 8; ++q)
-                    if (v[q] > bv) { bv = v[q]; bc = cl[q]; }   // classes ascend within a lane
+                for (int q = 1; q < KL; ++q)
+                    if (v[nt][q] > bv) { bv = v[nt][q]; bc = cl[nt][q]; }   // lower classes first
 #pragma unroll
                 for (int o = 16; o <= 32; o <<= 1) {
                     const float ov = __shfl_xor(bv, o, 64);
@@ -396,12 +438,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                 packed |= (uint32_t)bc << (8 * k);
                 if (cand8 && g == 0 && pkt < n) cand8[(size_t)pkt * a.topk + k] = (uint8_t)bc;
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (cl[q] == bc) v[q] = -INFINITY;
+                for (int q = 0; q < KL; ++q)
+                    if (cl[nt][q] == bc) v[nt][q] = -INFINITY;
                 // a removed class must never win again: push it below -inf ties
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (cl[q] == bc) cl[q] = 1 << 20;
+                for (int q = 0; q < KL; ++q)
+                    if (cl[nt][q] == bc) cl[nt][q] = 1 << 20;
             }
             if (cand && g == 0 && pkt < n) cand[pkt] = packed;
         }
@@ -476,8 +518,8 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
     const int H = (int)d->dims[1];
     if ((int)d->dims[2] != H || (H != 128 && H != 256))
         return fail(TANG_EINVAL, "hidden widths must be equal and 128 or 256");
-    if ((int)d->dims[3] != C || C < 1 || C > kOutPad)
-        return fail(TANG_EINVAL, "output width must equal the number of tuples (1..32)");
+    if ((int)d->dims[3] != C || C < 1 || C > TANG_MAX_TUPLES)
+        return fail(TANG_EINVAL, "output width must equal the number of tuples (1..256)");
     if (d->topk < 1 || d->topk > TANG_MAX_TOPK || (int)d->topk > C)
         return fail(TANG_EINVAL, "topk must be in 1..min(4, C)");
     if (p != TANG_FP32 && p != TANG_BF16 && p != TANG_FP8) return fail(TANG_EINVAL, "bad precision");
@@ -500,8 +542,10 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
     const int KB = p == TANG_FP32 ? 4 : p == TANG_BF16 ? 32 : 128;
     const int E = p == TANG_FP32 ? 1 : p == TANG_BF16 ? 8 : 32;
     const int esz = p == TANG_FP32 ? 4 : p == TANG_BF16 ? 2 : 1;
+    const int CP = kOutPad * ((C + kOutPad - 1) / kOutPad);  // classes padded to 32-blocks
     const int outs[3] = {H, H, C}, ins[3] = {104, H, H};
-    const int outp[3] = {H, H, kOutPad}, inp[3] = {kInPad, H, H};
+    const int outp[3] = {H, H, CP}, inp[3] = {kInPad, H, H};
+    m.w3frags = (uint32_t)(CP / 16 * (H / KB) * 64);
     for (int l = 0; l < 3; ++l) {
         float s_w = 1.0f, inv_w = 1.0f, s_a = 1.0f;
         if (p == TANG_FP8) {
@@ -542,7 +586,7 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
         m.bytes += buf.size();
     }
     // FP8 hidden biases are stored prescaled by the next layer's inverse activation scale
-    std::vector<float> bias(2 * H + kOutPad, 0.0f);
+    std::vector<float> bias(2 * H + CP, 0.0f);
     for (int k = 0; k < H; ++k) {
         bias[k] = p == TANG_FP8 ? b[0][k] * m.inv_a[1] : b[0][k];
         bias[H + k] = p == TANG_FP8 ? b[1][k] * m.inv_a[2] : b[1][k];
@@ -561,7 +605,7 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
 
 namespace {
 
-template <int PREC, int H, int NT, int LDSM, int WAVES = 8>
+template <int PREC, int H, int NT, int LDSM, int WAVES = 8, int OUTB = 1>
 hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, uint32_t* cand,
                     float* logits, uint8_t* cand8, hipStream_t s) {
     using F = typename FragT<PREC>::T;
@@ -569,9 +613,9 @@ hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, u
     constexpr size_t n1 = (H / 16) * (kInPad / KB) * 64, n2 = (H / 16) * (H / KB) * 64,
                      n3 = 2 * (H / KB) * 64;
     const size_t lds = ((LDSM & 1) ? n1 : 0) * sizeof(F) + ((LDSM & 2) ? n2 : 0) * sizeof(F) +
-                       ((LDSM & 4) ? n3 : 0) * sizeof(F) + (2 * H + kOutPad) * sizeof(float) +
+                       ((LDSM & 4) ? n3 : 0) * sizeof(F) + (2 * H + kOutPad * OUTB) * sizeof(float) +
                        (PREC == TANG_BF16 ? 256 * 16 : PREC == TANG_FP8 ? 256 * 8 : 0);
-    auto kern = k_mlp<PREC, H, NT, LDSM, WAVES>;
+    auto kern = k_mlp<PREC, H, NT, LDSM, WAVES, OUTB>;
     static int attr_done = 0;  // per instantiation
     if (!attr_done) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -592,6 +636,8 @@ hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, u
     MlpArgs a;
     a.n_out = m.n_out;
     a.topk = m.topk;
+    a.n3 = m.w3frags;
+    a.nbias = 2 * H + kOutPad * ((m.n_out + kOutPad - 1) / kOutPad);
     for (int l = 0; l < 3; ++l) { a.deq[l] = m.deq[l]; a.inv_a[l] = m.inv_a[l]; }
     for (int l = 0; l < 2; ++l) a.hs[l] = m.deq[l] * m.inv_a[l + 1];
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WAVES), lds, s,
@@ -617,7 +663,17 @@ hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size
         // LDSM: which layers' fragments sit in LDS (bit l = layer l) -- 160 KB per CU.
         // H = 256 runs 8 waves per CU (2 per SIMD): fewer than the register file would
         // hold, so that a chunked classify's search waves fit beside them.
-        if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 7>(m, h, k, c, lg, c8, s);
+        // More than 32 tuples: up to 8 blocks of 32 classes, W3 read from L2.
+        const bool wide = m.n_out > kOutPad;
+        if (wide) {
+            if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 3, 8, 8>(m, h, k, c, lg, c8, s);
+            else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0, 8, 8>(m, h, k, c, lg, c8, s);
+            else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 3, 8, 8>(m, h, k, c, lg, c8, s);
+            else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 2, 8, 8>(m, h, k, c, lg, c8, s);
+            else if (m.hidden == 128) e = launch_t<TANG_FP8, 128, 2, 3, 8, 8>(m, h, k, c, lg, c8, s);
+            else e = launch_t<TANG_FP8, 256, 2, 3, 8, 8>(m, h, k, c, lg, c8, s);
+        }
+        else if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 7>(m, h, k, c, lg, c8, s);
         else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0>(m, h, k, c, lg, c8, s);
         else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 7>(m, h, k, c, lg, c8, s);
         else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 6, 8>(m, h, k, c, lg, c8, s);

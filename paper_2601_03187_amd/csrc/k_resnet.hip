@@ -176,9 +176,12 @@ __global__ __launch_bounds__(512) void k_res_dense(const uint16_t* __restrict__ 
     }
 }
 
-// Output layer (C <= 32 scores, no activation) and top-k. Workgroup: 4 waves, each 64
-// headers (4 column tiles) x 32 classes (2 row tiles). A header's 32 scores sit in the 4
-// lanes c, c+16, c+32, c+48 (8 each); ties go to the lower class.
+// Output layer (C scores, no activation) and top-k. Workgroup: 4 waves, each 64 headers
+// (4 column tiles); classes in blocks of 32 (2 row tiles), ncb = ceil(C / 32) of them. A
+// header's scores of a block sit in the 4 lanes c, c+16, c+32, c+48; each lane keeps a
+// running top-4 of the classes it holds (a strictly larger score displaces, so ties keep
+// the lower class), which contains the lane's share of any top-k (k <= 4); the top-k is
+// then taken across the 4 lanes, ties to the lower class.
 __global__ __launch_bounds__(256) void k_res_out(const uint16_t* __restrict__ in,
                                                  const uint16_t* __restrict__ w,
                                                  const float* __restrict__ bias, uint32_t m,
@@ -187,53 +190,78 @@ __global__ __launch_bounds__(256) void k_res_out(const uint16_t* __restrict__ in
                                                  uint8_t* __restrict__ cand8) {
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u, g = lane >> 4, r = lane & 15u;
     const uint32_t p0 = (blockIdx.x * 4u + wave) * 64u;
+    const int ncb = (C + 31) / 32;
     const __amdgpu_buffer_rsrc_t ri = rsrc(in, m * (uint32_t)(kW * 2));
-    const __amdgpu_buffer_rsrc_t rw = rsrc(w, (uint32_t)(32 * kW * 2));
-    const uint32_t aoff = r * (kW * 2) + g * 16u;
+    const __amdgpu_buffer_rsrc_t rw = rsrc(w, (uint32_t)(32 * ncb * kW * 2));
     const uint32_t boff = (p0 + r) * (kW * 2) + g * 16u;
-    f4 acc[2][4];
+    float v[4][4];
+    int cl[4][4];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-        const f4 bv = *reinterpret_cast<const f4*>(bias + 16 * mt + 4 * g);
+    for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = bv;
-    }
+        for (int q = 0; q < 4; ++q) {
+            v[nt][q] = -INFINITY;
+            cl[nt][q] = 1 << 20;
+        }
+    for (int cb = 0; cb < ncb; ++cb) {
+        const uint32_t aoff = (32u * cb + r) * (kW * 2) + g * 16u;
+        f4 acc[2][4];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const f4 bv = *reinterpret_cast<const f4*>(bias + 32 * cb + 16 * mt + 4 * g);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = bv;
+        }
 #pragma unroll 2
-    for (uint32_t kb = 0; kb < kW / 32; ++kb) {
-        u32x4 A[2], B[4];
+        for (uint32_t kb = 0; kb < kW / 32; ++kb) {
+            u32x4 A[2], B[4];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-            A[mt] = __builtin_amdgcn_raw_buffer_load_b128(rw, aoff, mt * 16 * kW * 2 + kb * 64, 0);
+            for (int mt = 0; mt < 2; ++mt)
+                A[mt] = __builtin_amdgcn_raw_buffer_load_b128(rw, aoff, mt * 16 * kW * 2 + kb * 64, 0);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-            B[nt] = __builtin_amdgcn_raw_buffer_load_b128(ri, boff, nt * 16 * kW * 2 + kb * 64, 0);
+            for (int nt = 0; nt < 4; ++nt)
+                B[nt] = __builtin_amdgcn_raw_buffer_load_b128(ri, boff, nt * 16 * kW * 2 + kb * 64, 0);
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+            for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mma(A[mt], B[nt], acc[mt][nt]);
+                for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mma(A[mt], B[nt], acc[mt][nt]);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const uint32_t pkt = p0 + 16 * nt + r;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = 32 * cb + 16 * mt + 4 * (int)g + q;
+                    const float val = acc[mt][nt][q];
+                    if (logits && pkt < m && c < C) logits[(size_t)pkt * C + c] = val;
+                    float x = (c < C && val == val) ? val : -INFINITY;
+                    int xc = c;
+#pragma unroll
+                    for (int s2 = 0; s2 < 4; ++s2) {
+                        if (x > v[nt][s2]) {
+                            const float tv = v[nt][s2];
+                            const int tc = cl[nt][s2];
+                            v[nt][s2] = x;
+                            cl[nt][s2] = xc;
+                            x = tv;
+                            xc = tc;
+                        }
+                    }
+                }
+        }
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const uint32_t pkt = p0 + 16 * nt + r;
-        float v[8];
-        int cl[8];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int c = 16 * mt + 4 * (int)g + q;
-                const float val = acc[mt][nt][q];
-                if (logits && pkt < m && c < C) logits[(size_t)pkt * C + c] = val;
-                v[4 * mt + q] = (c < C && val == val) ? val : -INFINITY;
-                cl[4 * mt + q] = c;
-            }
         uint32_t packed = 0;
         for (int k = 0; k < topk; ++k) {
-            float bv = v[0];
-            int bc = cl[0];
+            float bv = v[nt][0];
+            int bc = cl[nt][0];
 #pragma unroll
-            for (int q = 1; q < 8; ++q)
-                if (v[q] > bv) { bv = v[q]; bc = cl[q]; }  // classes ascend within a lane
+            for (int q = 1; q < 4; ++q)
+                if (v[nt][q] > bv) { bv = v[nt][q]; bc = cl[nt][q]; }
 #pragma unroll
             for (int o = 16; o <= 32; o <<= 1) {
                 const float ov = __shfl_xor(bv, o, 64);
@@ -243,8 +271,8 @@ __global__ __launch_bounds__(256) void k_res_out(const uint16_t* __restrict__ in
             packed |= (uint32_t)bc << (8 * k);
             if (cand8 && g == 0 && pkt < m) cand8[(size_t)pkt * topk + k] = (uint8_t)bc;
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (cl[q] == bc) { v[q] = -INFINITY; cl[q] = 1 << 20; }
+            for (int q = 0; q < 4; ++q)
+                if (cl[nt][q] == bc) { v[nt][q] = -INFINITY; cl[nt][q] = 1 << 20; }
         }
         if (cand && g == 0 && pkt < m) cand[pkt] = packed;
     }
@@ -266,8 +294,8 @@ int resnet_prepare(tang_ruleset_t* rs, const tang_resnet_desc_t* d, const float*
     const int C = (int)rs->sigs.size();
     if (d->width != (uint32_t)kW) return fail(TANG_EINVAL, "residual model width must be 512");
     if (d->n_blocks < 1 || d->n_blocks > 16) return fail(TANG_EINVAL, "n_blocks must be in 1..16");
-    if ((int)d->n_out != C || C < 1 || C > kOutPad)
-        return fail(TANG_EINVAL, "output width must equal the number of tuples (1..32)");
+    if ((int)d->n_out != C || C < 1 || C > TANG_MAX_TUPLES)
+        return fail(TANG_EINVAL, "output width must equal the number of tuples (1..256)");
     if (d->topk < 1 || d->topk > TANG_MAX_TOPK || (int)d->topk > C)
         return fail(TANG_EINVAL, "topk must be in 1..min(4, C)");
     if (p != TANG_BF16) return fail(TANG_EINVAL, "the residual model runs in BF16");
@@ -285,13 +313,14 @@ int resnet_prepare(tang_ruleset_t* rs, const tang_resnet_desc_t* d, const float*
     std::vector<float> win((size_t)kW * 8, 0.0f);
     for (int n = 0; n < kW; ++n)
         for (int q = 0; q < 7; ++q) win[(size_t)n * 8 + q] = W[0][(size_t)n * 7 + q];
-    // biases: input layer, 2 per block, output (32, zero past C)
-    std::vector<float> bias((size_t)(1 + 2 * nb) * kW + kOutPad, 0.0f);
+    // biases: input layer, 2 per block, output (classes padded to 32-blocks, zero past C)
+    const int CP = kOutPad * ((C + kOutPad - 1) / kOutPad);
+    std::vector<float> bias((size_t)(1 + 2 * nb) * kW + CP, 0.0f);
     for (int l = 0; l < 1 + 2 * nb; ++l)
         for (int n = 0; n < kW; ++n) bias[(size_t)l * kW + n] = b[l][n];
     for (int c = 0; c < C; ++c) bias[(size_t)(1 + 2 * nb) * kW + c] = b[L - 1][c];
-    // BF16 weights: the block layers [512][512] each, then the output layer [32][512]
-    std::vector<uint16_t> w((size_t)2 * nb * kW * kW + (size_t)kOutPad * kW, 0);
+    // BF16 weights: the block layers [512][512] each, then the output layer [CP][512]
+    std::vector<uint16_t> w((size_t)2 * nb * kW * kW + (size_t)CP * kW, 0);
     for (int l = 0; l < 2 * nb; ++l)
         for (size_t k = 0; k < (size_t)kW * kW; ++k) w[(size_t)l * kW * kW + k] = to_bf16(W[1 + l][k]);
     for (int c = 0; c < C; ++c)

@@ -64,7 +64,7 @@ void probe_host(const tang_ruleset_t* rs, uint32_t t, const tang_header_t& p, Ho
     }
     const uint32_t keys[4][2] = {{kSubDp, p.dp}, {kSubSp, p.sp}, {kSubProto, p.proto}, {kSubRest, 0u}};
     for (const auto& q : keys) {
-        auto s = rs->bucket_of.find({t | (q[0] << 5), bi, q[1]});
+        auto s = rs->bucket_of.find({t | (q[0] << kKindShift), bi, q[1]});
         if (s != rs->bucket_of.end()) scan_members(rs, rs->buckets[s->second], t, p, b, c);
     }
 }
@@ -88,12 +88,17 @@ int search_host(const tang_ruleset_t* rs, const tang_header_t* hdr, const uint32
         for (size_t i = lo; i < hi; ++i) {
             const tang_header_t& p = hdr[i];
             HostBest b;
-            uint32_t probed = 0, c0 = 0xFFu;
+            uint32_t probed[4], n_probed = 0, c0 = ~0u;
+            auto was_probed = [&](uint32_t t) {
+                for (uint32_t j = 0; j < n_probed; ++j)
+                    if (probed[j] == t) return true;
+                return false;
+            };
             for (uint32_t k = 0; k < kcand; ++k) {
                 const uint32_t t = (cand[i] >> (8 * k)) & 0xFFu;
                 if (k == 0) c0 = t;
-                if (t >= ntup || ((probed >> t) & 1u)) continue;
-                probed |= 1u << t;
+                if (t >= ntup || was_probed(t)) continue;
+                probed[n_probed++] = t;
                 probe_host(rs, t, p, b, c);
             }
             const bool found = b.id != TANG_NO_MATCH;
@@ -101,7 +106,7 @@ int search_host(const tang_ruleset_t* rs, const tang_header_t* hdr, const uint32
             if (exact || !found) {
                 for (uint32_t t : order) {
                     if (rs->tuple_best[t] >= b.key) break;
-                    if ((probed >> t) & 1u) continue;
+                    if (was_probed(t)) continue;
                     probe_host(rs, t, p, b, c);
                 }
             }

@@ -21,17 +21,18 @@ namespace tang {
 //
 // Slot (16 B): one bucket of the global open-addressing table. The key is the full
 // (tuple, SIP & mask_t, DIP & mask_t), so an answer never depends on the hash function.
-//   tl = tuple << 24 | bucket length; kEmptyTL marks a never-used slot.
+//   tl = tuple << 20 | bucket length; kEmptyTL marks a never-used slot.
 //   off = first record of the bucket in the record array.
 struct alignas(16) Slot {
     uint32_t ms, md, tl, off;
 };
 constexpr uint32_t kEmptyTL = 0xFFFFFFFFu;
-constexpr uint32_t kMaxBucketLen = 0x00FFFFFFu;
+constexpr uint32_t kTlShift = 20;
+constexpr uint32_t kMaxBucketLen = (1u << kTlShift) - 1u;
 
 // Long buckets are split. A bucket that would hold more than kSplitAt rules keeps its
 // slot only as a marker (len 0, off = kSplit | bucket index); its rules move to four
-// sub-lists stored in the same table under keys (tuple | kind << 5, bucket index, value):
+// sub-lists stored in the same table under keys (tuple | kind << 8, bucket index, value):
 //   kSubDp    rules with an exact DP, value = that DP
 //   kSubSp    rules with an exact SP (DP not exact), value = that SP
 //   kSubProto rules with an exact protocol and no exact port, value = the protocol
@@ -42,12 +43,18 @@ constexpr uint32_t kMaxBucketLen = 0x00FFFFFFu;
 constexpr uint32_t kSplit = 0x80000000u;
 constexpr uint32_t kSplitAt = 32;
 enum : uint32_t { kSubDp = 1, kSubSp = 2, kSubProto = 3, kSubRest = 4 };
+constexpr uint32_t kKindShift = 8;   // tuples < 256; tuple | kind << 8 fits the slot's 12 bits
+
+// Conflict masks: one word per rule (in the record) for rulesets of at most 32 tuples,
+// kMaskWords words per rule (a side array indexed like the records) up to 256 tuples.
+constexpr int kMaskWords = 8;
 
 // Rec (32 B): one rule as the bucket scan reads it. Two 16-byte loads.
 //   sip, dip : prefix values, bits beyond the length zeroed
 //   sp, dp   : lo | hi << 16 (inclusive)
 //   meta     : sip_len (bits 0-5) | dip_len (6-11) | proto (12-19) | exact-proto (20)
-//              | tuple (21-25)
+//              | tuple (21-31)
+//   cmask    : conflict mask of a ruleset of at most 32 tuples (wider ones: side array)
 //   cmask    : conflict tuples -- tuples that hold a higher-priority rule whose box
 //              meets this rule's box (a superset after deletes)
 //   prio, id : the (priority, id) key; kDead marks a vacated record
@@ -64,7 +71,7 @@ __host__ __device__ inline uint32_t meta_sl(uint32_t m) { return m & 63u; }
 __host__ __device__ inline uint32_t meta_dl(uint32_t m) { return (m >> 6) & 63u; }
 __host__ __device__ inline uint32_t meta_proto(uint32_t m) { return (m >> 12) & 255u; }
 __host__ __device__ inline uint32_t meta_exact(uint32_t m) { return (m >> 20) & 1u; }
-__host__ __device__ inline uint32_t meta_tuple(uint32_t m) { return (m >> 21) & 31u; }
+__host__ __device__ inline uint32_t meta_tuple(uint32_t m) { return (m >> 21) & 2047u; }
 
 // Prefix mask of length l (0..32): the top l bits; l = 0 gives 0 (no shift by 32).
 __host__ __device__ inline uint32_t pmask(uint32_t l) {
@@ -80,11 +87,13 @@ struct TupleTable {
     TupleDev t[TANG_MAX_TUPLES];
     uint8_t order[TANG_MAX_TUPLES];  // tuple indices by ascending best key
     uint32_t rank_prio[TANG_MAX_TUPLES], rank_id[TANG_MAX_TUPLES];  // best keys in that order
-    uint32_t prefix[TANG_MAX_TUPLES + 1];  // prefix[k]: bits of the k tuples of lowest best key
+    // prefix[k]: the k tuples of lowest best key, as mask words
+    uint32_t prefix[TANG_MAX_TUPLES + 1][kMaskWords];
     uint32_t n;                       // number of tuples
-    uint32_t all_mask;                // bits of all tuples
+    uint32_t all_mask[kMaskWords];    // bits of all tuples
     uint32_t slot_mask;               // slots - 1
     uint32_t filter_mask;             // filter bits - 1
+    uint32_t nw;                      // mask words of this ruleset (1 or kMaskWords)
 };
 
 // Key hash: two chained MurmurHash3 32-bit finalisers (fmix32, Appleby, public domain),
@@ -150,6 +159,7 @@ struct ModelDev {
     tang_precision_t prec = TANG_FP32;
     int hidden = 0;
     int n_out = 0;    // C
+    uint32_t w3frags = 0;  // output-layer weight fragments (classes padded to 32-blocks)
     int topk = 1;
     // Weight fragments for the three layers in MFMA A-operand order, and biases.
     void* w[3] = {nullptr, nullptr, nullptr};
@@ -210,11 +220,13 @@ struct tang_ruleset_s {
     std::vector<tang::Slot> slots;                 // host mirror of the slot table
     std::vector<uint32_t> filter;                  // host mirror of the bucket filter
     uint32_t rec_used = 0, rec_cap = 0;
+    uint32_t nw = 1;   // conflict-mask words per rule (fixed at build: 1, or kMaskWords)
 
     // device state
     tang::Slot* d_slots = nullptr;
     uint32_t* d_filter = nullptr;
     tang::Rec* d_recs = nullptr;
+    uint32_t* d_cmask = nullptr;   // nw > 1: kMaskWords words per record position
     tang::TupleTable* d_tt = nullptr;
     tang::StatsDev* d_stats = nullptr;
     hipStream_t upd_stream = nullptr;
@@ -256,12 +268,17 @@ int apply_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n);
 // Kernel launchers (k_classify.hip, k_build.hip, k_mlp.hip).
 hipError_t launch_classify(const tang_ruleset_t* rs, const tang_header_t* d_hdr,
                            uint32_t* d_out, size_t n, int kcand, hipStream_t s, bool stats);
-hipError_t launch_conflict_build(const BoxDev* d_boxes, size_t n, Rec* d_recs, uint32_t all_mask,
+hipError_t launch_conflict_build(const BoxDev* d_boxes, size_t n, Rec* d_recs, uint32_t* d_cmask,
+                                 uint32_t nw, const uint32_t* all_mask,
                                  hipStream_t s);
-hipError_t launch_conflict_update(Rec* d_recs, uint32_t rec_used, const uint32_t* d_new_pos,
-                                  uint32_t n_new, hipStream_t s);
+hipError_t launch_conflict_update(Rec* d_recs, uint32_t* d_cmask, uint32_t nw, uint32_t rec_used,
+                                  const uint32_t* d_new_pos, uint32_t n_new, hipStream_t s);
 hipError_t launch_move_records(Rec* d_recs, const Rec* d_src_recs, const uint32_t* d_src,
                                const uint32_t* d_dst, uint32_t n, Rec* d_stage, hipStream_t s);
+// nw > 1: the mask rows move with their records (the same src / dst lists; new sources
+// get zero rows), through a stage of n rows.
+hipError_t launch_move_masks(uint32_t* d_cmask, const uint32_t* d_src, const uint32_t* d_dst,
+                             uint32_t n, uint32_t* d_stage, hipStream_t s);
 hipError_t launch_scatter_slots(Slot* d_slots, const uint32_t* d_idx, const Slot* d_val,
                                 uint32_t n, hipStream_t s);
 // Batches of at least two chunks of this many headers, with a BF16 or FP8 model and no

@@ -20,29 +20,29 @@ bool key_less(const tang_rule_t& a, const tang_rule_t& b) { return key_of(a) < k
 // Slot contents of bucket b: a split marker, or the bucket's list.
 Slot slot_value(const tang_ruleset_t* rs, uint32_t b) {
     const auto& bk = rs->buckets[b];
-    if (bk.split) return Slot{bk.ms, bk.md, bk.t << 24, kSplit | b};
-    return Slot{bk.ms, bk.md, (bk.t << 24) | (uint32_t)bk.members.size(), bk.off};
+    if (bk.split) return Slot{bk.ms, bk.md, bk.t << kTlShift, kSplit | b};
+    return Slot{bk.ms, bk.md, (bk.t << kTlShift) | (uint32_t)bk.members.size(), bk.off};
 }
 
 // Linear probing from the hash position to the first empty slot.
 uint32_t slot_insert(std::vector<Slot>& slots, const Slot& v) {
     uint32_t mask = (uint32_t)slots.size() - 1;
-    uint32_t h = slot_of(key_hash(v.tl >> 24, v.ms, v.md)) & mask;
+    uint32_t h = slot_of(key_hash(v.tl >> kTlShift, v.ms, v.md)) & mask;
     while (slots[h].tl != kEmptyTL) h = (h + 1) & mask;
     slots[h] = v;
     return h;
 }
 
-bool is_main(const tang_ruleset_t::Bucket& bk) { return (bk.t >> 5) == 0; }
+bool is_main(const tang_ruleset_t::Bucket& bk) { return (bk.t >> kKindShift) == 0; }
 
 // Sub-list key of rule h inside the split main bucket b.
 tang_ruleset_t::BKey sub_key(const tang_ruleset_t* rs, uint32_t b, uint32_t h) {
     const tang_rule_t& r = rs->rules[h].r;
     const uint32_t t = rs->buckets[b].t;
-    if (r.dp_lo == r.dp_hi) return {t | (kSubDp << 5), b, r.dp_lo};
-    if (r.sp_lo == r.sp_hi) return {t | (kSubSp << 5), b, r.sp_lo};
-    if (r.proto_mask) return {t | (kSubProto << 5), b, r.proto};
-    return {t | (kSubRest << 5), b, 0u};
+    if (r.dp_lo == r.dp_hi) return {t | (kSubDp << kKindShift), b, r.dp_lo};
+    if (r.sp_lo == r.sp_hi) return {t | (kSubSp << kKindShift), b, r.sp_lo};
+    if (r.proto_mask) return {t | (kSubProto << kKindShift), b, r.proto};
+    return {t | (kSubRest << kKindShift), b, 0u};
 }
 
 uint32_t find_or_add_bucket(tang_ruleset_t* rs, const tang_ruleset_t::BKey& k) {
@@ -166,10 +166,12 @@ TupleTable make_tuple_table(const tang_ruleset_t* rs) {
         tt.order[i] = (uint8_t)ord[i];
         tt.rank_prio[i] = (uint32_t)(rs->tuple_best[ord[i]] >> 32);
         tt.rank_id[i] = (uint32_t)rs->tuple_best[ord[i]];
-        tt.prefix[i + 1] = tt.prefix[i] | (1u << ord[i]);
+        for (int w = 0; w < kMaskWords; ++w) tt.prefix[i + 1][w] = tt.prefix[i][w];
+        tt.prefix[i + 1][ord[i] >> 5] |= 1u << (ord[i] & 31u);
     }
     tt.n = n;
-    tt.all_mask = n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u);
+    for (uint32_t t = 0; t < n; ++t) tt.all_mask[t >> 5] |= 1u << (t & 31u);
+    tt.nw = rs->nw;
     tt.slot_mask = rs->slots.empty() ? 0 : (uint32_t)rs->slots.size() - 1;
     tt.filter_mask = rs->filter.empty() ? 0 : (uint32_t)rs->filter.size() * 32u - 1u;
     return tt;
@@ -203,12 +205,13 @@ int build_host(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
         while (t < rs->sigs.size() && rs->sigs[t] != sig) ++t;
         if (t == rs->sigs.size()) {
             if (rs->sigs.size() == TANG_MAX_TUPLES)
-                return fail(TANG_EINVAL, "more than 32 distinct (sip_len, dip_len) signatures");
+                return fail(TANG_EINVAL, "more than 256 distinct (sip_len, dip_len) signatures");
             rs->sigs.push_back(sig);
             rs->tuple_best.push_back(key_of(hr.r));
         }
         hr.tuple = (uint32_t)t;
     }
+    rs->nw = rs->sigs.size() <= 32 ? 1u : (uint32_t)kMaskWords;
 
     // Buckets keyed by (tuple, masked SIP, masked DIP), members in key order.
     for (uint32_t h : order) {
@@ -248,6 +251,10 @@ int upload_all(tang_ruleset_t* rs) {
     TANG_HIP(hipMemcpy(rs->d_filter, rs->filter.data(), rs->filter.size() * sizeof(uint32_t),
                        hipMemcpyHostToDevice));
     TANG_HIP(hipMalloc(&rs->d_recs, (size_t)rs->rec_cap * sizeof(Rec)));
+    if (rs->nw > 1) {
+        TANG_HIP(hipMalloc(&rs->d_cmask, (size_t)rs->rec_cap * kMaskWords * sizeof(uint32_t)));
+        TANG_HIP(hipMemset(rs->d_cmask, 0, (size_t)rs->rec_cap * kMaskWords * sizeof(uint32_t)));
+    }
     TANG_HIP(hipMalloc(&rs->d_tt, sizeof(TupleTable)));
     TANG_HIP(hipMalloc(&rs->d_stats, kStatCopies * sizeof(StatsDev)));
 
@@ -284,7 +291,9 @@ int upload_all(tang_ruleset_t* rs) {
         TANG_HIP(hipMalloc(&d_boxes, boxes.size() * sizeof(BoxDev)));
         hipError_t e = hipMemcpy(d_boxes, boxes.data(), boxes.size() * sizeof(BoxDev),
                                  hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = launch_conflict_build(d_boxes, boxes.size(), rs->d_recs, tt.all_mask, s);
+        if (e == hipSuccess)
+            e = launch_conflict_build(d_boxes, boxes.size(), rs->d_recs, rs->d_cmask, rs->nw,
+                                      rs->d_tt->all_mask, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         hipFree(d_boxes);
         if (e != hipSuccess) return hip_fail(e, "conflict-mask build");
@@ -331,6 +340,17 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
         std::vector<Rec> tail(ncap - rs->rec_used, dead_rec());
         TANG_HIP(hipMemcpyAsync(nrec + rs->rec_used, tail.data(), tail.size() * sizeof(Rec),
                                 hipMemcpyHostToDevice, s));
+        if (rs->nw > 1) {
+            uint32_t* nmask = nullptr;
+            const size_t row = kMaskWords * sizeof(uint32_t);
+            TANG_HIP(hipMalloc(&nmask, (size_t)ncap * row));
+            TANG_HIP(hipMemsetAsync(nmask, 0, (size_t)ncap * row, s));
+            TANG_HIP(hipMemcpyAsync(nmask, rs->d_cmask, (size_t)rs->rec_used * row,
+                                    hipMemcpyDeviceToDevice, s));
+            TANG_HIP(hipStreamSynchronize(s));
+            TANG_HIP(hipFree(rs->d_cmask));
+            rs->d_cmask = nmask;
+        }
         TANG_HIP(hipStreamSynchronize(s));
         TANG_HIP(hipFree(rs->d_recs));
         rs->d_recs = nrec;
@@ -398,6 +418,15 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
         if (e == hipSuccess)
             e = launch_move_records(rs->d_recs, (const Rec*)d_new, (const uint32_t*)d_src,
                                     (const uint32_t*)d_dst, (uint32_t)dst.size(), (Rec*)d_stage, s);
+        if (e == hipSuccess && rs->nw > 1) {
+            void* d_mstage = nullptr;
+            e = hipMalloc(&d_mstage, dst.size() * kMaskWords * sizeof(uint32_t));
+            if (e == hipSuccess) {
+                tmp.push_back(d_mstage);
+                e = launch_move_masks(rs->d_cmask, (const uint32_t*)d_src, (const uint32_t*)d_dst,
+                                      (uint32_t)dst.size(), (uint32_t*)d_mstage, s);
+            }
+        }
     }
     // slots
     if (e == hipSuccess) {
@@ -449,8 +478,8 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
         void* d_pos = nullptr;
         e = dev_copy(pos.data(), pos.size() * 4, &d_pos);
         if (e == hipSuccess)
-            e = launch_conflict_update(rs->d_recs, rs->rec_used, (const uint32_t*)d_pos,
-                                       (uint32_t)pos.size(), s);
+            e = launch_conflict_update(rs->d_recs, rs->d_cmask, rs->nw, rs->rec_used,
+                                       (const uint32_t*)d_pos, (uint32_t)pos.size(), s);
     }
     hipError_t e2 = hipStreamSynchronize(s);
     for (void* p : tmp) hipFree(p);
@@ -473,8 +502,11 @@ int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
         if (rs->id2h.count(rules[i].id) || !seen.emplace(rules[i].id, 1).second)
             return fail(TANG_EEXIST, "rule id " + std::to_string(rules[i].id) + " is live or repeated");
         if (choose_tuple(sigs, rules[i].sip_len, rules[i].dip_len) < 0) {
-            if (sigs.size() == TANG_MAX_TUPLES)
-                return fail(TANG_EINVAL, "insert would need a tuple beyond 32");
+            if (sigs.size() == (rs->nw == 1 ? 32u : (size_t)TANG_MAX_TUPLES))
+                return fail(TANG_EINVAL, rs->nw == 1
+                                             ? "insert would need a 33rd tuple (the ruleset was built "
+                                               "with one conflict-mask word)"
+                                             : "insert would need a tuple beyond 256");
             sigs.emplace_back(rules[i].sip_len, rules[i].dip_len);
         }
     }
@@ -524,7 +556,7 @@ int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
         } else {
             for (size_t b = nb_before; b < rs->buckets.size(); ++b) {
                 auto& bk = rs->buckets[b];
-                bk.slot = slot_insert(rs->slots, Slot{bk.ms, bk.md, bk.t << 24, 0});
+                bk.slot = slot_insert(rs->slots, Slot{bk.ms, bk.md, bk.t << kTlShift, 0});
                 if (is_main(bk)) filter_set(rs->filter, bk.t, bk.ms, bk.md);
             }
             filter_dirty = true;

@@ -47,6 +47,9 @@ NO_MATCH = 0xFFFFFFFF
 
 IP_LENS = np.array([32, 24, 16, 8, 0], dtype=np.int64)
 IP_LEN_P = np.array([0.40, 0.20, 0.15, 0.10, 0.15])
+# a wide tuple space: 12 lengths per field, uniform -> 144 (SIP, DIP) signatures, in
+# the range of the paper's rulesets (31-391 tuples)
+WIDE_IP_LENS = np.array([32, 30, 28, 26, 24, 22, 20, 18, 16, 12, 8, 0], dtype=np.int64)
 MIX_IP_LENS = np.array([16, 8, 0], dtype=np.int64)
 MIX_IP_LEN_P = np.array([0.25, 0.25, 0.50])
 PORT_P = np.array([0.60, 0.25, 0.15])            # wildcard, exact, range
@@ -78,14 +81,20 @@ def _draw_ports(rng, n, probs):
     return lo.astype(np.uint16), hi.astype(np.uint16), cls
 
 
-def make_rules(n: int, seed: int, ordering: str = "specificity", mix: float = 0.0) -> np.ndarray:
-    """Draw `n` 5-field rules. Returns a RULE_DTYPE array with priority = id = index."""
+def make_rules(n: int, seed: int, ordering: str = "specificity", mix: float = 0.0,
+               wide: bool = False) -> np.ndarray:
+    """Draw `n` 5-field rules. Returns a RULE_DTYPE array with priority = id = index.
+    wide: IP prefix lengths uniform over WIDE_IP_LENS (a tuple space of ~144 tuples)."""
     if ordering not in ("specificity", "literal"):
         raise ValueError(ordering)
     rng = _rng(seed)
     heavy = rng.random(n) < mix
-    sl = rng.choice(IP_LENS, size=n, p=IP_LEN_P)
-    dl = rng.choice(IP_LENS, size=n, p=IP_LEN_P)
+    if wide:
+        sl = rng.choice(WIDE_IP_LENS, size=n)
+        dl = rng.choice(WIDE_IP_LENS, size=n)
+    else:
+        sl = rng.choice(IP_LENS, size=n, p=IP_LEN_P)
+        dl = rng.choice(IP_LENS, size=n, p=IP_LEN_P)
     if heavy.any():
         k = int(heavy.sum())
         sl[heavy] = rng.choice(MIX_IP_LENS, size=k, p=MIX_IP_LEN_P)
@@ -242,6 +251,9 @@ CONFIGS = {
     # the paper's dynamic experiment (Sec. 7.4) scaled to one GPU: windows of deletes and
     # inserts with a SIP prefix length the tuple set does not have (a drifting
     # distribution; one new length keeps a rebuilt tuple space within 32 tuples)
+    # a wide tuple space (144 tuples): 512k rules, 16M Zipf headers
+    "c7_wide": dict(n_rules=524_288, n_pkts=16_777_216, frac_in=1.0, zipf=1.0, mix=0.0,
+                    hidden=256, seed=707),
     "c6_drift": dict(n_rules=65_536, windows=10, per_window=2_000, n_pkts=1_000_000,
                      frac_in=0.80, hidden=256, seed=606, sip_lengths=(4,)),
 }

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libtang.so")
 
 TANG_NO_MATCH = 0xFFFFFFFF
 TANG_HOST_ONLY = -1
-TANG_MAX_TUPLES = 32
+TANG_MAX_TUPLES = 256
 TANG_FP32, TANG_BF16, TANG_FP8 = 0, 1, 2
 PRECISIONS = {"fp32": TANG_FP32, "bf16": TANG_BF16, "fp8": TANG_FP8}
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTFOUND", -4: "EEXIST", -5: "EDEVICE",
@@ -80,6 +80,7 @@ _sigs = {
     "tang_ruleset_num_rules": (ctypes.c_size_t, [_P]),
     "tang_ruleset_rule_tuple": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
     "tang_ruleset_conflict_mask": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
+    "tang_ruleset_conflict_mask_words": (ctypes.c_int, [_P, ctypes.c_uint32, _P, ctypes.c_uint32]),
     "tang_ruleset_device_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "tang_ruleset_set_stream": (ctypes.c_int, [_P, _P]),
     "tang_model_load": (ctypes.c_int, [_P, ctypes.POINTER(tang_mlp_desc_t), _P, _P, ctypes.c_int, _P]),
@@ -181,9 +182,10 @@ def tang_ruleset_rule_tuple(rs: int, rule_id: int) -> int:
 
 
 def tang_ruleset_conflict_mask(rs: int, rule_id: int) -> int:
-    m = ctypes.c_uint32()
-    _check(_lib.tang_ruleset_conflict_mask(rs, rule_id, ctypes.byref(m)))
-    return int(m.value)
+    """The whole conflict mask as a Python int (bit t = tuple t, up to 256 tuples)."""
+    words = (ctypes.c_uint32 * 8)()
+    _check(_lib.tang_ruleset_conflict_mask_words(rs, rule_id, ctypes.cast(words, _P), 8))
+    return sum(int(w) << (32 * i) for i, w in enumerate(words))
 
 
 def tang_ruleset_device_bytes(rs: int) -> int:

@@ -67,9 +67,10 @@ def test_host_tuple_space_matches_table1(golden_tab_rules):
         T.tang_ruleset_destroy(rs)
 
 
-@pytest.mark.parametrize("ordering,mix", [("literal", 0.0), ("specificity", 0.25)])
-def test_host_tuples_equal_reference(ordering, mix):
-    rules = synth.make_rules(3000, seed=17, ordering=ordering, mix=mix)
+@pytest.mark.parametrize("ordering,mix,wide", [("literal", 0.0, False), ("specificity", 0.25, False),
+                                               ("specificity", 0.0, True)])
+def test_host_tuples_equal_reference(ordering, mix, wide):
+    rules = synth.make_rules(3000, seed=17, ordering=ordering, mix=mix, wide=wide)
     rng = np.random.default_rng(0)
     rules = rules[rng.permutation(len(rules))]  # input order must not matter
     rs = T.tang_ruleset_create(T.TANG_HOST_ONLY, rules)
@@ -156,13 +157,53 @@ def test_empty_ruleset_and_too_many_signatures():
     rs = T.tang_ruleset_create(T.TANG_HOST_ONLY, np.zeros(0, dtype=synth.RULE_DTYPE))
     assert T.tang_ruleset_num_tuples(rs) == 0 and T.tang_ruleset_num_rules(rs) == 0
     T.tang_ruleset_destroy(rs)
-    r = np.zeros(33, dtype=synth.RULE_DTYPE)
-    r["sp_hi"] = r["dp_hi"] = 65535
-    r["sip_len"] = np.arange(33)
-    r["id"] = np.arange(33)
+    def sigs(n):
+        r = np.zeros(n, dtype=synth.RULE_DTYPE)
+        r["sp_hi"] = r["dp_hi"] = 65535
+        r["sip_len"] = np.arange(n) % 33
+        r["dip_len"] = np.arange(n) // 33
+        r["id"] = r["priority"] = np.arange(n)
+        return r
+    rs = T.tang_ruleset_create(T.TANG_HOST_ONLY, sigs(T.TANG_MAX_TUPLES))
+    assert T.tang_ruleset_num_tuples(rs) == T.TANG_MAX_TUPLES
+    T.tang_ruleset_destroy(rs)
     with pytest.raises(T.TangError) as e:
-        T.tang_ruleset_create(T.TANG_HOST_ONLY, r)
+        T.tang_ruleset_create(T.TANG_HOST_ONLY, sigs(T.TANG_MAX_TUPLES + 1))
     assert e.value.name == "EINVAL"
+
+
+def test_appending_a_tuple_past_the_mask_width():
+    """A ruleset built with at most 32 tuples keeps one conflict-mask word per rule, so an
+    insert that needs a 33rd tuple fails (EINVAL, nothing changes); one built with more
+    appends tuples up to 256."""
+    def grid(pairs, first_id):
+        r = np.zeros(len(pairs), dtype=synth.RULE_DTYPE)
+        r["sp_hi"] = r["dp_hi"] = 65535
+        r["sip_len"] = [a for a, _ in pairs]
+        r["dip_len"] = [b for _, b in pairs]
+        r["id"] = r["priority"] = np.arange(first_id, first_id + len(pairs))
+        return r
+    narrow = grid([(a, 32) for a in range(1, 33)], 0)       # 32 tuples, none dominates (0, 0)
+    rs = T.tang_ruleset_create(T.TANG_HOST_ONLY, narrow)
+    try:
+        assert T.tang_ruleset_num_tuples(rs) == 32
+        with pytest.raises(T.TangError) as e:
+            T.tang_insert(rs, grid([(0, 0)], 100))
+        assert e.value.name == "EINVAL"
+        assert T.tang_ruleset_num_tuples(rs) == 32 and T.tang_ruleset_num_rules(rs) == 32
+    finally:
+        T.tang_ruleset_destroy(rs)
+    wide = grid([(a, b) for a in range(1, 33) for b in (16, 32)], 0)   # 64 tuples
+    rs = T.tang_ruleset_create(T.TANG_HOST_ONLY, wide)
+    try:
+        T.tang_insert(rs, grid([(0, 8)], 1000))
+        T.tang_insert(rs, grid([(0, 0)], 1001))
+        T.tang_insert(rs, grid([(0, 12)], 1002))   # (0, 8) dominates: restricted insertion
+        assert T.tang_ruleset_num_tuples(rs) == 66
+        assert [T.tang_ruleset_rule_tuple(rs, i) for i in (1000, 1001, 1002)] == [64, 65, 64]
+        assert T.tang_ruleset_tuple(rs, 64) == (0, 8) and T.tang_ruleset_tuple(rs, 65) == (0, 0)
+    finally:
+        T.tang_ruleset_destroy(rs)
 
 
 def test_coarse_rule_counter_follows_restricted_insertion(golden_tab_rules):

@@ -33,11 +33,14 @@ def _hidden_amax(X, Ws, bs):
     return out
 
 
+@pytest.mark.parametrize("wide", [False, True])
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("hidden", [128, 256])
-def test_logits_and_candidates_vs_oracle(prec, hidden):
+def test_logits_and_candidates_vs_oracle(prec, hidden, wide):
+    """wide: 144 tuples, so the output layer runs over several 64-class blocks with a
+    running top-k."""
     torch_cuda()
-    rules = synth.make_rules(3000, seed=41)
+    rules = synth.make_rules(3000, seed=41, wide=wide)
     hdr = synth.make_packets(rules, 3001, seed=42, frac_in=0.7)  # ragged: not a tile multiple
     rs = T.tang_ruleset_create(0, rules)
     try:
@@ -63,7 +66,8 @@ def test_logits_and_candidates_vs_oracle(prec, hidden):
         margin = srt[:, -1] - srt[:, -2]
         rows_ok = (err <= tight).all(axis=1) & (margin > 2 * tight.max(axis=1))
         top = orc.topk(want, 2)
-        assert rows_ok.mean() > 0.25   # enough rows with a clear winner to make the check bite
+        # enough rows with a clear winner to make the check bite (144 classes crowd the top)
+        assert rows_ok.mean() > (0.05 if wide else 0.25)
         assert np.array_equal(cand[rows_ok, 0], top[rows_ok, 0])
         third = np.sort(want, axis=1)[:, -3]
         rows2 = rows_ok & ((srt[:, -2] - third) > 2 * tight.max(axis=1))

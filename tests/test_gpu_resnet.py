@@ -54,8 +54,8 @@ def _near_boundary(pre, e):
     return orc.bf16_round(np.maximum(pre + e, 0)) != orc.bf16_round(np.maximum(pre - e, 0))
 
 
-def _ruleset(n=1500, seed=61):
-    rules = synth.make_rules(n, seed=seed)
+def _ruleset(n=1500, seed=61, wide=False):
+    rules = synth.make_rules(n, seed=seed, wide=wide)
     rs = T.tang_ruleset_create(0, rules)
     return rules, rs, T.tang_ruleset_num_tuples(rs)
 
@@ -93,11 +93,13 @@ def test_permutation_blocks_exact_across_chunks():
         T.tang_ruleset_destroy(rs)
 
 
-@pytest.mark.parametrize("n_blocks", [1, 6])
-def test_random_weights_within_bound_and_candidates(n_blocks):
-    """The paper's depth (6 blocks) and a single block, random weights."""
+@pytest.mark.parametrize("n_blocks,wide", [(1, False), (6, False), (2, True)])
+def test_random_weights_within_bound_and_candidates(n_blocks, wide):
+    """The paper's depth (6 blocks) and a single block, random weights; and a 144-tuple
+    ruleset (several 64-class output blocks with a running top-k)."""
     torch_cuda()
-    rules, rs, C = _ruleset(seed=63)
+    rules, rs, C = _ruleset(seed=63, wide=wide)
+    assert C > 128 if wide else C <= 32
     try:
         Ws, bs = _random_model(C, n_blocks, np.random.default_rng(10 + n_blocks))
         T.tang_model_load_resnet(rs, Ws, bs, "bf16", topk=1)

@@ -89,3 +89,23 @@ def test_argument_errors():
         assert len(T.tang_search_host(rs, hdr[:0])) == 0
     finally:
         T.tang_ruleset_destroy(rs)
+
+
+def test_wide_tuple_space_exact_and_paper_modes():
+    """144 tuples (12 prefix lengths per field): the host tuple space and both search modes
+    with candidates anywhere in 0..C-1, including tuple indices past 32."""
+    rules = synth.make_rules(4000, seed=35, wide=True)
+    hdr = synth.make_packets(rules, 12_000, seed=36, frac_in=0.8)
+    truth = orc.classify(rules, hdr)
+    rs = T.tang_ruleset_create(T.TANG_HOST_ONLY, rules)
+    try:
+        C = T.tang_ruleset_num_tuples(rs)
+        assert C == len(orc.tuples_first_appearance(rules)) and C > 128
+        rng = np.random.default_rng(37)
+        c = rng.integers(0, C, (len(hdr), 2))
+        cand = (c[:, 0].astype(np.uint32) | (c[:, 1].astype(np.uint32) << np.uint32(8))).astype(np.uint32)
+        assert np.array_equal(T.tang_search_host(rs, hdr, cand, 2, threads=4, exact=True), truth)
+        paper = T.tang_search_host(rs, hdr, cand, 2, threads=4, exact=False)
+        assert np.array_equal(paper, _paper_answers(rules, hdr, cand, 2, truth))
+    finally:
+        T.tang_ruleset_destroy(rs)
