@@ -419,7 +419,54 @@ def other_configs(args, rules3, rs3, d_hdr3, prec3):
                                    "oracle_checked": int(len(samp)),
                                    "mismatches": int((got[samp] != want).sum())}
     log(f"[bench] c3 with 80% rule-sampled headers: {res['c3_512k_80pct_inside']['mpps']:.0f} Mpps")
+    del d_hdr, d_out
+    res["c7_wide"] = bench_wide(args)
     return res
+
+
+def bench_wide(args):
+    """A wide tuple space: 524,288 rules over 144 (SIP, DIP) signatures (12 prefix lengths
+    per field), 16M Zipf headers; no model, and a trained 104-256-256-144 MLP in BF16 and
+    FP8 (top-1). Mpps, probes per header, and a seeded 20,000-header oracle sample."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as orc
+    from paper_2601_03187_amd import synth, train
+    from paper_2601_03187_amd import tang as T
+
+    cfg = synth.CONFIGS["c7_wide"]
+    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], wide=True)
+    n = cfg["n_pkts"]
+    hdr = synth.make_packets(rules, n, seed=cfg["seed"] + 1, frac_in=cfg["frac_in"], zipf_s=cfg["zipf"])
+    rs = T.tang_ruleset_create(0, rules)
+    C = T.tang_ruleset_num_tuples(rs)
+    d_hdr = torch.from_numpy(hdr.view(np.uint8).reshape(-1)).cuda()
+    d_out = torch.empty(n, dtype=torch.int32, device="cuda")
+    samp = np.sort(np.random.default_rng(13).choice(n, 20_000, replace=False))
+    want = orc.classify(rules, hdr[samp])
+    out = {"rules": len(rules), "tuples": C, "headers": n, "hidden": cfg["hidden"]}
+
+    def run(name):
+        st = T.tang_classify(rs, d_hdr, d_out, n, torch.cuda.current_stream(), want_stats=True)
+        got = d_out.cpu().numpy().view(np.uint32)
+        ms = time_classify(T, rs, d_hdr, d_out, n, args.steps)
+        out[name] = {"mpps": n / ms / 1e3, "ms_per_batch": ms, "probes_per_pkt": st["probes"] / n,
+                     "records_per_pkt": st["records"] / n, "top1_hit_rate": st["top1_hits"] / n,
+                     "fallback_rate": st["fallbacks"] / n, "oracle_checked": int(len(samp)),
+                     "mismatches": int((got[samp] != want).sum())}
+        log(f"[bench] c7_wide {name}: {out[name]['mpps']:.0f} Mpps, "
+            f"{out[name]['probes_per_pkt']:.2f} probes/pkt, {out[name]['mismatches']} mismatches")
+
+    run("no_model")
+    Ws, bs, sc, acc = train.fit(rs, rules, hdr[:200_000], cfg["hidden"], steps=args.train_steps,
+                                seed=1, device="cuda")
+    out["train_top1"] = acc
+    for p in ("bf16", "fp8"):
+        T.tang_model_load(rs, Ws, bs, p, topk=1, act_scales=sc if p == "fp8" else None)
+        run(p)
+    T.tang_ruleset_destroy(rs)
+    return out
 
 
 def bench_hybrid(rs, hdr, d_hdr, want):
