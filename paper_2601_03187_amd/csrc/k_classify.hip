@@ -18,6 +18,8 @@
 namespace tang {
 namespace {
 
+constexpr uint32_t kNoTuple = 0xFFFFFFFFu;
+
 struct Best {
     uint32_t prio, id, cmask, tuple, pos;   // pos: record index (for wide conflict masks)
 };
@@ -153,6 +155,11 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
     __shared__ uint32_t s_prefix[NT + 1][NW];
     __shared__ uint32_t s_all[NW];
     __shared__ uint32_t s_misc[4];
+    // field pre-check (wide tuple spaces only): distinct lengths and their tuple masks
+    constexpr int NF = NW > 1 ? 33 : 1;
+    __shared__ uint32_t s_flen[2][NF];
+    __shared__ uint32_t s_fmask[2][NF][NW];
+    __shared__ uint32_t s_nflen[2];
     const int tid = threadIdx.x;
     for (uint32_t k = tid; k < NT; k += 256u) {
         s_t[k] = ttg->t[k];
@@ -160,6 +167,12 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
     }
     for (uint32_t k = tid; k < (NT + 1) * NW; k += 256u) s_prefix[k / NW][k % NW] = ttg->prefix[k / NW][k % NW];
     if (tid < NW) s_all[tid] = ttg->all_mask[tid];
+    if constexpr (NW > 1) {
+        for (uint32_t k = tid; k < 2u * NF * NW; k += 256u)
+            s_fmask[k / (NF * NW)][(k / NW) % NF][k % NW] = ttg->fmask[k / (NF * NW)][(k / NW) % NF][k % NW];
+        if (tid < 2 * NF) s_flen[tid / NF][tid % NF] = ttg->flen[tid / NF][tid % NF];
+        if (tid < 2) s_nflen[tid] = ttg->nflen[tid];
+    }
     if (tid == 0) {
         s_misc[0] = ttg->n;
         s_misc[2] = ttg->slot_mask;
@@ -235,25 +248,90 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
             for (int w = 0; w < NW; ++w) todo[w] &= s_prefix[k][w];
         }
     }
-    // Phase 1: the filter bits of every remaining tuple, eight tuples per batch with their
-    // loads issued back to back (batches no lane of the wave needs are skipped);
-    // `hits` keeps the tuples whose bit is set.
-    uint32_t hits[NW];
+    // Wide tuple spaces, headers with many tuples left (all that matched nothing yet, and
+    // those with a wide conflict mask): check the field keys of the distinct lengths of
+    // each field (eight loads at a time) and keep only the tuples whose SIP and DIP
+    // lengths both passed. Below 25 tuples three more batches would not pay.
+    if constexpr (NW > 1) {
+        uint32_t left = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        hits[w] = 0;
-        const uint32_t wave_todo = wave_or(todo[w]);
-        if (!wave_todo) continue;
-        for (uint32_t t0 = 0; t0 < 32u && 32u * w + t0 < ntup; t0 += 8) {
-            if (!((wave_todo >> t0) & 0xFFu)) continue;
+        for (int w = 0; w < NW; ++w) left += __builtin_popcount(todo[w]);
+        const bool many = left > 24u;
+        if (wave_or(many ? 1u : 0u)) {
+            unsigned long long pass[2] = {0ull, 0ull};
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const uint32_t nl = s_nflen[side], v = side == 0 ? sip : dip;
+                for (uint32_t i0 = 0; i0 < nl; i0 += 8) {
+                    if (STATS) ++n_rounds;
+                    uint32_t wd[8], pos[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        wd[q] = 0;
+                        pos[q] = 0;
+                        if (many && i0 + q < nl) {
+                            const uint32_t len = s_flen[side][i0 + q];
+                            const uint32_t bit = field_filter_hash(side, len, v & pmask(len)) & filter_mask;
+                            wd[q] = filter[bit >> 5];
+                            pos[q] = bit & 31u;
+                            if (STATS) ++n_filter;
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        pass[side] |= (unsigned long long)((wd[q] >> pos[q]) & 1u) << (i0 + q);
+                }
+            }
+            if (many) {
+                uint32_t keep[2][NW];
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) keep[side][w] = 0;
+                    for (unsigned long long m = pass[side]; m; m &= m - 1ull) {
+                        const uint32_t j = (uint32_t)__builtin_ctzll(m);
+#pragma unroll
+                        for (int w = 0; w < NW; ++w) keep[side][w] |= s_fmask[side][j][w];
+                    }
+                }
+#pragma unroll
+                for (int w = 0; w < NW; ++w) todo[w] &= keep[0][w] & keep[1][w];
+            }
+        }
+    }
+    // Phase 1: the filter bits of every remaining tuple, eight tuples per batch with their
+    // loads issued back to back; `hits` keeps the tuples whose bit is set. With one mask
+    // word a batch is eight consecutive tuples (batches no lane of the wave needs are
+    // skipped); with several, each lane takes its own next eight tuples, so the wave runs
+    // as many batches as its busiest lane needs rather than one per eight tuple indices.
+    uint32_t hits[NW];
+    if constexpr (NW > 1) {
+        uint32_t rem[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            hits[w] = 0;
+            rem[w] = todo[w];
+        }
+        for (;;) {
+            uint32_t left = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) left |= rem[w];
+            if (!wave_or(left)) break;  // each batch takes up to eight tuples of every lane
             if (STATS) ++n_rounds;
-            uint32_t wd[8], pos[8];
+            uint32_t tq[8], wd[8], pos[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const uint32_t t = 32u * w + t0 + q;
+                uint32_t t = kNoTuple;
+#pragma unroll
+                for (int w = 0; w < NW; ++w)
+                    if (t == kNoTuple && rem[w]) {
+                        t = 32u * w + (uint32_t)__builtin_ctz(rem[w]);
+                        rem[w] &= rem[w] - 1u;
+                    }
+                tq[q] = t;
                 wd[q] = 0;
                 pos[q] = 0;
-                if ((todo[w] >> (t0 + q)) & 1u) {  // t < ntup: todo holds only existing tuples
+                if (t != kNoTuple) {
                     const uint32_t bit =
                         filter_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask) & filter_mask;
                     wd[q] = filter[bit >> 5];
@@ -262,7 +340,39 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) hits[w] |= ((wd[q] >> pos[q]) & 1u) << (t0 + q);
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t on = (wd[q] >> pos[q]) & 1u;
+#pragma unroll
+                for (int w = 0; w < NW; ++w)
+                    hits[w] |= ((tq[q] >> 5) == (uint32_t)w ? on : 0u) << (tq[q] & 31u);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            hits[w] = 0;
+            const uint32_t wave_todo = wave_or(todo[w]);
+            if (!wave_todo) continue;
+            for (uint32_t t0 = 0; t0 < 32u && 32u * w + t0 < ntup; t0 += 8) {
+                if (!((wave_todo >> t0) & 0xFFu)) continue;
+                if (STATS) ++n_rounds;
+                uint32_t wd[8], pos[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint32_t t = 32u * w + t0 + q;
+                    wd[q] = 0;
+                    pos[q] = 0;
+                    if ((todo[w] >> (t0 + q)) & 1u) {  // t < ntup: todo holds only existing tuples
+                        const uint32_t bit =
+                            filter_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask) & filter_mask;
+                        wd[q] = filter[bit >> 5];
+                        pos[q] = bit & 31u;
+                        if (STATS) ++n_filter;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) hits[w] |= ((wd[q] >> pos[q]) & 1u) << (t0 + q);
+            }
         }
     }
     // Phase 2: each lane searches its own passing tuples (so a wave takes as many steps as

@@ -17,7 +17,9 @@
 // Weight fragments live in LDS when they fit (160 KB per CU) and are read from global
 // (L2-resident) otherwise; biases and the per-layer FP8 scales stay FP32.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
+#include <type_traits>
 
 #include "tang_internal.hpp"
 
@@ -219,6 +221,8 @@ __device__ __forceinline__ void epi_hidden(const f4 (&acc)[NT], int mt, const fl
     }
 }
 
+constexpr int kNoClass = 1 << 20;  // an empty or removed top-k slot (above every class)
+
 // OUTB: most blocks of 32 output classes (1, or 8 for up to 256 tuples; the W3 fragments
 // of a multi-block model are read from L2).
 template <int PREC, int H, int NT, int LDSM, int WAVES, int OUTB>
@@ -354,8 +358,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
         }
         // layer 3: H -> C in blocks of 32 classes (two 16-row tiles). With one block each
         // lane's 8 scores go straight to the top-k; with more, each lane keeps a running
-        // top-4 of the classes it holds (a strictly larger score displaces, so ties keep
-        // the lower class, as classes ascend block by block).
+        // top-k of the classes it holds (a strictly larger score displaces, so ties keep
+        // the lower class, as classes ascend block by block; there a NaN or -inf score
+        // counts as -FLT_MAX, so every real class beats an empty slot and a padded class).
+        // With one block a NaN score counts as -inf and ties go to the lower class.
         const float* sb3 = sb + 2 * H;
         constexpr int KL = OUTB == 1 ? 8 : 4;
         float v[NT][KL];
@@ -366,7 +372,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
 #pragma unroll
                 for (int q = 0; q < KL; ++q) {
                     v[nt][q] = -INFINITY;
-                    cl[nt][q] = 1 << 20;
+                    cl[nt][q] = kNoClass;
                 }
         }
         const int ncb = OUTB == 1 ? 1 : (C + 31) / 32;
@@ -385,38 +391,45 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
-            // scores
+            // scores; the running top-k keeps topk slots (1, 2, or 4 for 3 and 4; a uniform
+            // branch per block picks the count)
+            auto scores = [&](auto slots) {
+                constexpr int KS = decltype(slots)::value;
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const uint32_t pkt = pbase + nt * 16 + col;
+                for (int nt = 0; nt < NT; ++nt) {
+                    const uint32_t pkt = pbase + nt * 16 + col;
 #pragma unroll
-                for (int mt = 0; mt < 2; ++mt) {
+                    for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int c = 32 * cb + 16 * mt + 4 * g + r;
-                        float val = (PREC == TANG_FP8 ? z[mt][nt][r] * a.deq[2] : z[mt][nt][r]) + sb3[c];
-                        if (logits && pkt < n && c < C) logits[(size_t)pkt * C + c] = val;
-                        float x = (c < C && val == val) ? val : -INFINITY;
-                        if constexpr (OUTB == 1) {
-                            v[nt][4 * mt + r] = x;
-                            cl[nt][4 * mt + r] = c;
-                        } else {
-                            int xc = c;
+                        for (int r = 0; r < 4; ++r) {
+                            const int c = 32 * cb + 16 * mt + 4 * g + r;
+                            float val = (PREC == TANG_FP8 ? z[mt][nt][r] * a.deq[2] : z[mt][nt][r]) + sb3[c];
+                            if (logits && pkt < n && c < C) logits[(size_t)pkt * C + c] = val;
+                            if constexpr (OUTB == 1) {
+                                v[nt][4 * mt + r] = (c < C && val == val) ? val : -INFINITY;
+                                cl[nt][4 * mt + r] = c;
+                            } else {
+                                float x = c < C ? (val == val ? fmaxf(val, -FLT_MAX) : -FLT_MAX) : -INFINITY;
+                                int xc = c;
 #pragma unroll
-                            for (int q = 0; q < KL; ++q) {
-                                if (x > v[nt][q]) {
-                                    const float tv = v[nt][q];
-                                    const int tc = cl[nt][q];
-                                    v[nt][q] = x;
-                                    cl[nt][q] = xc;
-                                    x = tv;
-                                    xc = tc;
+                                for (int q = 0; q < KS; ++q) {
+                                    if (x > v[nt][q]) {
+                                        const float tv = v[nt][q];
+                                        const int tc = cl[nt][q];
+                                        v[nt][q] = x;
+                                        cl[nt][q] = xc;
+                                        x = tv;
+                                        xc = tc;
+                                    }
                                 }
                             }
                         }
                     }
                 }
-            }
+            };
+            if (OUTB > 1 && a.topk == 1) scores(std::integral_constant<int, 1>{});
+            else if (OUTB > 1 && a.topk == 2) scores(std::integral_constant<int, 2>{});
+            else scores(std::integral_constant<int, KL>{});
         }
         // top-k with ties to the lower tuple index
 #pragma unroll
@@ -443,7 +456,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                 // a removed class must never win again: push it below -inf ties
 #pragma unroll
                 for (int q = 0; q < KL; ++q)
-                    if (cl[nt][q] == bc) cl[nt][q] = 1 << 20;
+                    if (cl[nt][q] == bc) cl[nt][q] = kNoClass;
             }
             if (cand && g == 0 && pkt < n) cand[pkt] = packed;
         }

@@ -94,6 +94,11 @@ struct TupleTable {
     uint32_t slot_mask;               // slots - 1
     uint32_t filter_mask;             // filter bits - 1
     uint32_t nw;                      // mask words of this ruleset (1 or kMaskWords)
+    // Field pre-check of wide tuple spaces: per field (0 = SIP, 1 = DIP) the distinct prefix
+    // lengths of the tuples, and per length the mask of the tuples that have it.
+    uint8_t flen[2][33];
+    uint32_t nflen[2];
+    uint32_t fmask[2][33][kMaskWords];
 };
 
 // Key hash: two chained MurmurHash3 32-bit finalisers (fmix32, Appleby, public domain),
@@ -133,6 +138,16 @@ __host__ __device__ inline uint32_t filter_hash(uint32_t t, uint32_t ms, uint32_
 // after deletes). A header's masked key whose bit is clear has no bucket in that tuple,
 // so the slot walk is skipped; at >= 32 bits per bucket about 3% of absent keys pass.
 // Sized to stay L2-resident (2 MB at 512k rules).
+//
+// Wide tuple spaces (more than 32 tuples) also put each bucket's two field keys in the
+// filter -- (SIP length, masked SIP) and (DIP length, masked DIP), under salts that no
+// tuple index reaches -- at 64 bits per bucket. A tuple can hold a bucket for a header
+// only if both of the header's field keys for the tuple's lengths are present, so a
+// header first checks one bit per distinct length of each field instead of one per tuple.
+constexpr uint32_t kFieldSalt = 1024;
+__host__ __device__ inline uint32_t field_filter_hash(uint32_t side, uint32_t len, uint32_t v) {
+    return side == 0 ? filter_hash(kFieldSalt + len, v, 0u) : filter_hash(kFieldSalt + 64u + len, 0u, v);
+}
 
 // Device-side counters for tang_stats_t (kStatCopies copies, summed on the host).
 struct StatsDev {

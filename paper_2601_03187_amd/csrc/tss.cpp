@@ -74,20 +74,32 @@ std::vector<uint32_t> split_bucket(tang_ruleset_t* rs, uint32_t b) {
     return touched;
 }
 
-void filter_set(std::vector<uint32_t>& f, uint32_t t, uint32_t ms, uint32_t md) {
-    const uint32_t b = filter_hash(t, ms, md) & ((uint32_t)f.size() * 32u - 1u);
+void filter_bit(std::vector<uint32_t>& f, uint32_t h) {
+    const uint32_t b = h & ((uint32_t)f.size() * 32u - 1u);
     f[b >> 5] |= 1u << (b & 31u);
 }
 
-// Slot table at load <= 1/4 (short walks) and the bucket filter at >= 32 bits per bucket.
+// The filter bits of a main bucket: its key, and in a wide tuple space its field keys.
+void filter_add(tang_ruleset_t* rs, const tang_ruleset_t::Bucket& bk) {
+    filter_bit(rs->filter, filter_hash(bk.t, bk.ms, bk.md));
+    if (rs->nw > 1) {
+        filter_bit(rs->filter, field_filter_hash(0, rs->sigs[bk.t].first, bk.ms));
+        filter_bit(rs->filter, field_filter_hash(1, rs->sigs[bk.t].second, bk.md));
+    }
+}
+
+uint64_t filter_bits_per_bucket(const tang_ruleset_t* rs) { return rs->nw > 1 ? 64 : 32; }
+
+// Slot table at load <= 1/4 (short walks) and the bucket filter at >= 32 bits per bucket
+// (64 with field keys).
 void rebuild_slots(tang_ruleset_t* rs) {
     const uint64_t nb = rs->buckets.size();
     rs->slots.assign(next_pow2(std::max<uint64_t>(1024, 4 * nb + 4)), Slot{0, 0, kEmptyTL, 0});
-    rs->filter.assign(std::max<uint64_t>(2048, next_pow2(32 * nb + 32) / 32), 0u);
+    rs->filter.assign(std::max<uint64_t>(2048, next_pow2(filter_bits_per_bucket(rs) * (nb + 1)) / 32), 0u);
     for (uint32_t b = 0; b < rs->buckets.size(); ++b) {
         auto& bk = rs->buckets[b];
         bk.slot = slot_insert(rs->slots, slot_value(rs, b));
-        if (is_main(bk)) filter_set(rs->filter, bk.t, bk.ms, bk.md);
+        if (is_main(bk)) filter_add(rs, bk);
     }
 }
 
@@ -172,6 +184,15 @@ TupleTable make_tuple_table(const tang_ruleset_t* rs) {
     tt.n = n;
     for (uint32_t t = 0; t < n; ++t) tt.all_mask[t >> 5] |= 1u << (t & 31u);
     tt.nw = rs->nw;
+    for (uint32_t t = 0; t < n; ++t) {
+        const uint8_t lens[2] = {rs->sigs[t].first, rs->sigs[t].second};
+        for (int side = 0; side < 2; ++side) {
+            uint32_t j = 0;
+            while (j < tt.nflen[side] && tt.flen[side][j] != lens[side]) ++j;
+            if (j == tt.nflen[side]) tt.flen[side][tt.nflen[side]++] = lens[side];
+            tt.fmask[side][j][t >> 5] |= 1u << (t & 31u);
+        }
+    }
     tt.slot_mask = rs->slots.empty() ? 0 : (uint32_t)rs->slots.size() - 1;
     tt.filter_mask = rs->filter.empty() ? 0 : (uint32_t)rs->filter.size() * 32u - 1u;
     return tt;
@@ -548,16 +569,16 @@ int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
     // new buckets need slots; grow the table when it would pass half full
     bool rehash = false, filter_dirty = false;
     if (rs->buckets.size() != nb_before) {
-        // keep the slot table at most 1/3 full and the filter at >= 16 bits per bucket
+        // keep the slot table at most 1/3 full and the filter at >= half its bits per bucket
         if (3 * rs->buckets.size() + 3 > rs->slots.size() ||
-            16 * rs->buckets.size() > rs->filter.size() * 32) {
+            filter_bits_per_bucket(rs) / 2 * rs->buckets.size() > rs->filter.size() * 32) {
             rebuild_slots(rs);
             rehash = true;
         } else {
             for (size_t b = nb_before; b < rs->buckets.size(); ++b) {
                 auto& bk = rs->buckets[b];
                 bk.slot = slot_insert(rs->slots, Slot{bk.ms, bk.md, bk.t << kTlShift, 0});
-                if (is_main(bk)) filter_set(rs->filter, bk.t, bk.ms, bk.md);
+                if (is_main(bk)) filter_add(rs, bk);
             }
             filter_dirty = true;
         }

@@ -77,19 +77,33 @@ def test_logits_and_candidates_vs_oracle(prec, hidden, wide):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
-def test_all_equal_scores_pick_lowest_indices(prec):
+@pytest.mark.parametrize("wide", [False, True])
+def test_all_equal_scores_pick_lowest_indices(prec, wide):
+    """Ties go to the lower tuple index, also across the 32-class blocks of a 144-tuple
+    output layer; NaN scores (a NaN bias) still yield valid, distinct candidates."""
     torch_cuda()
-    rules = synth.make_rules(500, seed=43)
+    rules = synth.make_rules(1500 if wide else 500, seed=43, wide=wide)
     hdr = synth.make_packets(rules, 100, seed=44, frac_in=0.5)
     rs = T.tang_ruleset_create(0, rules)
     try:
         C = T.tang_ruleset_num_tuples(rs)
         Ws, bs = train.constant_winner_weights(C, 128, 0)
         bs[2][:] = 0.0  # every score equal
-        T.tang_model_load(rs, Ws, bs, prec, topk=3, act_scales=[1, 1, 1] if prec == "fp8" else None)
-        logits, cand = mlp_dev(rs, hdr, C, topk=3)
-        assert (logits == 0).all()
-        assert (cand == np.array([0, 1, 2])).all()
+        sc = [1, 1, 1] if prec == "fp8" else None
+        for k in (1, 3, 4):
+            T.tang_model_load(rs, Ws, bs, prec, topk=k, act_scales=sc)
+            logits, cand = mlp_dev(rs, hdr, C, topk=k)
+            assert (logits == 0).all()
+            assert (cand == np.arange(k)).all(), k
+        bs[2][C - 1] = 1.0          # one winner in the last block, the rest tie
+        bs[2][C // 2] = 0.5
+        T.tang_model_load(rs, Ws, bs, prec, topk=3, act_scales=sc)
+        _, cand = mlp_dev(rs, hdr, C, topk=3)
+        assert (cand == np.array([C - 1, C // 2, 0])).all()
+        bs[2][:] = np.nan
+        T.tang_model_load(rs, Ws, bs, prec, topk=2, act_scales=sc)
+        _, cand = mlp_dev(rs, hdr, C, topk=2)
+        assert (cand < C).all() and (cand[:, 0] != cand[:, 1]).all()
     finally:
         T.tang_ruleset_destroy(rs)
 
