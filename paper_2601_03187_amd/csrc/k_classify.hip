@@ -39,6 +39,25 @@ __device__ __forceinline__ bool rec_match(const Rec& r, uint32_t sip, uint32_t d
     return ok;
 }
 
+// Whole-record and whole-slot loads (two and one 16-byte loads). Copying the structs
+// field by field lets the compiler split them into narrow loads sunk into the branches
+// that use each field: more load instructions per wave and dependent round trips
+// between them (priority and id first, the rest after the comparison).
+// An empty asm that takes all four words keeps each 16-byte load whole and in place.
+__device__ __forceinline__ uint4 load16(const void* p) {
+    uint4 a = *reinterpret_cast<const uint4*>(p);
+    asm volatile("" : "+v"(a.x), "+v"(a.y), "+v"(a.z), "+v"(a.w));
+    return a;
+}
+__device__ __forceinline__ Rec load_rec(const Rec* p) {
+    const uint4 a = load16(p), c = load16(reinterpret_cast<const uint4*>(p) + 1);
+    return Rec{a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+}
+__device__ __forceinline__ Slot load_slot(const Slot* p) {
+    const uint4 a = load16(p);
+    return Slot{a.x, a.y, a.z, a.w};
+}
+
 // Compares one list of records in (priority, id) order: the first match is its best;
 // the scan stops there or at the first record that cannot beat the current answer.
 template <bool STATS>
@@ -46,7 +65,7 @@ __device__ __forceinline__ void scan_list(uint32_t off, uint32_t len, uint32_t s
                                           uint32_t sp, uint32_t dp, uint32_t proto,
                                           const Rec* __restrict__ recs, Best& b, uint32_t& n_recs) {
     for (uint32_t k = 0; k < len; ++k) {
-        const Rec r = recs[off + k];
+        const Rec r = load_rec(recs + off + k);
         if (STATS) ++n_recs;
         if (!kless(r.prio, r.id, b.prio, b.id)) break;
         if (rec_match(r, sip, dip, sp, dp, proto)) {
@@ -65,7 +84,7 @@ __device__ __forceinline__ Slot find_slot(uint64_t h64, uint32_t tk, uint32_t k0
                                           uint32_t& n_slots) {
     uint32_t h = slot_of(h64) & slot_mask;
     for (uint32_t step = 0; step <= slot_mask; ++step) {
-        const Slot s = slots[h];
+        const Slot s = load_slot(slots + h);
         if (STATS) ++n_slots;
         if (s.tl == kEmptyTL || (s.ms == k0 && s.md == k1 && (s.tl >> kTlShift) == tk)) return s;
         h = (h + 1) & slot_mask;
