@@ -97,14 +97,21 @@ __global__ __launch_bounds__(256) void k_res_input(const uint4* __restrict__ hdr
 // One 512 x 512 layer: out = relu(W in + b [+ res]) over m header rows, BF16 in and out,
 // FP32 accumulation with the bias as the accumulator's start. Workgroup: 8 waves and 128
 // headers; wave w computes neurons 64w..64w+63 (4 row tiles) for all 128 headers (8 column
-// tiles). K advances 32 at a time. The headers' 32-wide K slice (128 x 64 bytes) is
-// shared by the 8 waves through LDS -- each thread copies 16 bytes of the next slice while
-// the current one is multiplied (double buffer, one barrier per step); rows are padded to
-// 80 bytes so that the 16 lanes of a 128-bit read hit 16 distinct groups of 4 banks. Each
-// wave reads its own weight rows straight from L2. Global loads of both operands are
-// issued two steps ahead (the activations come from the Infinity Cache or HBM). Rows past
-// m read as zero (buffer range check) and are not written.
-constexpr uint32_t kRowB = 80;   // bytes per header row of a K slice in LDS (64 + 16 pad)
+// tiles). K advances 32 at a time through a ring of three LDS stages, each holding the
+// K slice of all 512 weight rows (32 KB) and of the 128 header rows (8 KB). The slices go
+// straight from global memory into LDS (global_load_lds, 16 bytes per lane, lane l's
+// bytes landing at 16 l from the wave's base), so loads run three steps ahead of the
+// MFMAs without holding registers; each wave moves 4 KB of weights and 1 KB of headers
+// per step. Rows are 64 bytes with their four 16-byte chunks XOR-swizzled by row bits 1..3
+// (chunk c of row n at slot c ^ sw(n), sw(n) = ((n >> 1) ^ (n >> 2)) & 3): any 8, and any
+// 16, consecutive rows read at one chunk hit distinct 16-byte bank groups, so 128-bit
+// fragment reads are conflict-free whether the LDS serves 8 or 16 lanes per cycle (the
+// plain XOR by bits 2..3 left 4 conflict cycles per read). Header rows past m load row m - 1
+// instead (their columns are never written). One barrier per step: after it every
+// wave's loads for the next step have landed, and nobody still reads the stage that the
+// next loads overwrite.
+constexpr uint32_t kStageA = 512u * 64u, kStageB = 128u * 64u, kStage = kStageA + kStageB;
+__device__ __forceinline__ uint32_t sw(uint32_t row) { return ((row >> 1) ^ (row >> 2)) & 3u; }
 
 template <bool RES>
 __global__ __launch_bounds__(512) void k_res_dense(const uint16_t* __restrict__ in,
@@ -112,15 +119,21 @@ __global__ __launch_bounds__(512) void k_res_dense(const uint16_t* __restrict__ 
                                                    const float* __restrict__ bias,
                                                    const uint16_t* __restrict__ res,
                                                    uint16_t* __restrict__ out, uint32_t m) {
-    __shared__ __attribute__((aligned(16))) unsigned char sb[2][128 * kRowB];
-    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u, g = lane >> 4, r = lane & 15u;
+    __shared__ __attribute__((aligned(16))) unsigned char st0[kStage], st1[kStage], st2[kStage];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, g = lane >> 4, r = lane & 15u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint32_t p0 = blockIdx.x * 128u, n0 = wave * 64u;
-    const __amdgpu_buffer_rsrc_t ri = rsrc(in, m * (uint32_t)(kW * 2));
-    const __amdgpu_buffer_rsrc_t rw = rsrc(w, (uint32_t)(kW * kW * 2));
-    const uint32_t aoff = (n0 + r) * (kW * 2) + g * 16u;
-    // this thread's share of a K slice: header tid / 4, bytes 16 (tid % 4) .. + 15
-    const uint32_t coff = (p0 + (tid >> 2)) * (kW * 2) + (tid & 3u) * 16u;
-    const uint32_t cdst = (tid >> 2) * kRowB + (tid & 3u) * 16u;
+    // loads: lane l of an instruction fills row 16 j + l / 4 (j: the instruction's row
+    // block), slot l % 4, with chunk (l % 4) ^ sw(row); row blocks start at multiples of
+    // 16, so sw(row) = sw(l / 4)
+    const uint32_t lrow = lane >> 2, lchunk = (lane & 3u) ^ sw(lrow);
+    const unsigned char* wsrc = reinterpret_cast<const unsigned char*>(w) +
+                                (size_t)(n0 + lrow) * (kW * 2) + lchunk * 16u;
+    const uint32_t hrow = std::min(p0 + wave * 16u + lrow, m - 1u);
+    const unsigned char* hsrc = reinterpret_cast<const unsigned char*>(in) +
+                                (size_t)hrow * (kW * 2) + lchunk * 16u;
+    // fragment reads: row (tile base) + r, chunk g at its swizzled slot
+    const uint32_t rd = r * 64u + ((g ^ sw(r)) * 16u);
     f4 acc[4][8];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
@@ -128,32 +141,65 @@ __global__ __launch_bounds__(512) void k_res_dense(const uint16_t* __restrict__ 
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = bv;
     }
-    // loads run kD steps ahead through a ring of kR register slots (fully unrolled, so
-    // every slot index is a constant)
-    constexpr int kS = kW / 32, kD = 2, kR = kD + 1;
-    u32x4 A[kR][4], Bq[kR];
+    constexpr int kS = kW / 32;
+    auto stage = [&](int k) -> unsigned char* { return k % 3 == 0 ? st0 : k % 3 == 1 ? st1 : st2; };
     auto issue = [&](int kb) {
-        Bq[kb % kR] = __builtin_amdgcn_raw_buffer_load_b128(ri, coff, kb * 64, 0);
+        unsigned char* sd = stage(kb);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            __builtin_amdgcn_global_load_lds(
+                (void*)(wsrc + (size_t)j * 16u * (kW * 2) + kb * 64),
+                (__attribute__((address_space(3))) void*)(sd + (wave * 4u + j) * 1024u), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(
+            (void*)(hsrc + kb * 64), (__attribute__((address_space(3))) void*)(sd + kStageA + wave * 1024u),
+            16, 0, 0);
+    };
+    // Step hand-off: this wave's LDS reads are done and its loads for the stage read next
+    // have landed (s_waitcnt lgkmcnt(0) and vmcnt <= the loads issued since), then a bare
+    // barrier. __syncthreads() would add a workgroup release fence, which waits for every
+    // load in flight into LDS, the lookahead included; the empty asm statements keep the
+    // compiler from moving LDS accesses across the barrier.
+    constexpr int kLoadsPerStep = 5;
+    auto handoff = [&](int pending) {
+        if (pending) __builtin_amdgcn_s_waitcnt(0x0070 | kLoadsPerStep);
+        else __builtin_amdgcn_s_waitcnt(0x0070);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
+    // Fragments of step k are read from LDS during step k - 1, into the register set
+    // k & 1, so their latency hides behind a whole step of MFMAs. Stage k % 3 is refilled
+    // (step k + 3) during step k: every wave read it in step k - 1, before that step's
+    // closing barrier. Loads of step k + 2 must have landed by the barrier that closes
+    // step k, since step k + 1 reads them.
+    u32x4 FA[2][4], FB[2][8];
+    auto read = [&](int k) {
+        const unsigned char* sa = stage(k);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
-            A[kb % kR][mt] = __builtin_amdgcn_raw_buffer_load_b128(rw, aoff, mt * 16 * kW * 2 + kb * 64, 0);
-    };
+            FA[k & 1][mt] = *reinterpret_cast<const u32x4*>(sa + (n0 + 16u * mt) * 64u + rd);
 #pragma unroll
-    for (int kb = 0; kb < kD; ++kb) issue(kb);
-    *reinterpret_cast<u32x4*>(sb[0] + cdst) = Bq[0];
-    __syncthreads();
+        for (int nt = 0; nt < 8; ++nt)
+            FB[k & 1][nt] = *reinterpret_cast<const u32x4*>(sa + kStageA + 16u * nt * 64u + rd);
+    };
+    issue(0);
+    issue(1);
+    issue(2);
+    __builtin_amdgcn_s_waitcnt(0x0070 | (2 * kLoadsPerStep));
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    read(0);
+    handoff(1);
 #pragma unroll
     for (int kb = 0; kb < kS; ++kb) {
-        if (kb + kD < kS) issue(kb + kD);
-        const unsigned char* bt = sb[kb & 1];
+        if (kb + 1 < kS) read(kb + 1);
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) {
-            const u32x4 B = *reinterpret_cast<const u32x4*>(bt + (16 * nt + r) * kRowB + g * 16);
+        for (int nt = 0; nt < 8; ++nt)
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) acc[mt][nt] = mma(A[kb % kR][mt], B, acc[mt][nt]);
-        }
-        if (kb + 1 < kS) *reinterpret_cast<u32x4*>(sb[(kb + 1) & 1] + cdst) = Bq[(kb + 1) % kR];
-        __syncthreads();
+            for (int mt = 0; mt < 4; ++mt) acc[mt][nt] = mma(FA[kb & 1][mt], FB[kb & 1][nt], acc[mt][nt]);
+        if (kb + 3 < kS) issue(kb + 3);
+        if (kb + 2 < kS) handoff(kb + 3 < kS);
     }
 #pragma unroll
     for (int nt = 0; nt < 8; ++nt) {
