@@ -229,7 +229,7 @@ template <int PREC, int H, int NT, int LDSM, int WAVES, int OUTB>
 __global__ __launch_bounds__(64 * WAVES) void k_mlp(
     const uint4* __restrict__ hdr, uint32_t n, const typename FragT<PREC>::T* __restrict__ w1,
     const typename FragT<PREC>::T* __restrict__ w2, const typename FragT<PREC>::T* __restrict__ w3,
-    const float* __restrict__ bias_g, MlpArgs a, uint32_t* __restrict__ cand,
+    const u32x4* __restrict__ w1x3, const float* __restrict__ bias_g, MlpArgs a, uint32_t* __restrict__ cand,
     float* __restrict__ logits, uint8_t* __restrict__ cand8) {
     using F = typename FragT<PREC>::T;
     constexpr int KB = FragT<PREC>::KB;
@@ -258,8 +258,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
         if (LDSM & 2) copy16(s2, w2, n2 * sizeof(F));
         if (LDSM & 4) copy16(s3, w3, n3 * sizeof(F));
         copy16(sb, bias_g, a.nbias * sizeof(float));
-        if constexpr (PREC != TANG_FP32)
-            if (threadIdx.x < 256) Bits<PREC>::entry(threadIdx.x, stab + threadIdx.x * Bits<PREC>::kEntry);
+        // FP32 runs its input layer on BF16 MFMAs, so it builds the BF16 bit table
+        using BT = Bits<PREC == TANG_FP32 ? TANG_BF16 : PREC>;
+        if (threadIdx.x < 256) BT::entry(threadIdx.x, stab + threadIdx.x * BT::kEntry);
     }
     __syncthreads();
 
@@ -282,19 +283,48 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
             const uint32_t p = pbase + nt * 16 + col;
             hv[nt] = p < n ? hdr[p] : make_uint4(0, 0, 0, 0);
         }
-        // layer 1: bits -> H. When its fragments come from L2 (not LDS), the next tile's
-        // loads are issued before this tile's MFMAs so their latency is hidden.
+        // layer 1: bits -> H.
         F a0[KBNH][NT];
+        if constexpr (PREC == TANG_FP32) {
+            // FP32 weights against 0/1 inputs: W1 = hi + mid + lo, three BF16 planes that
+            // sum to it exactly, so each product with a bit is exact on a BF16 MFMA and
+            // the 16x16x32 instruction does 32 of them where 16x16x4 FP32 does 4; the
+            // accumulation stays FP32. Fragments (mt, kb, plane) come from L2; the other
+            // waves' layer-2 MFMAs cover their latency.
+            u32x4 xb[4][NT];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) xb[kb][nt] = Bits<TANG_BF16>::get(hv[nt], kb, g, stab);
+            const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)w1x3, 0, (uint32_t)(MTH * 12 * 64 * 16), 0x00020000);
+#pragma unroll
+            for (int mt = 0; mt < MTH; ++mt) {
+                u32x4 wf[12];
+#pragma unroll
+                for (int f = 0; f < 12; ++f)
+                    wf[f] = bload(rx, lane * 16u + sbase, (uint32_t)((mt * 12 + f) * 1024), (u32x4*)nullptr);
+                f4 acc[NT];
+                const f4 b0 = acc_init<PREC>(sb, mt, g);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[nt] = b0;
+#pragma unroll
+                for (int f = 0; f < 12; ++f)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[nt] = mma(wf[f], xb[f / 3][nt], acc[nt]);
+                epi_hidden<PREC, NT, KBNH>(acc, mt, sb, a.hs[0], g, a0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+        // When its fragments come from L2 (not LDS), the next tile's
+        // loads are issued before this tile's MFMAs so their latency is hidden.
         F pre[KBN1_USED];
         // BF16 / FP8: the input-bit fragments are built once per tile of headers
-        constexpr bool kBitsOnce = PREC != TANG_FP32;
-        F bits[kBitsOnce ? KBN1_USED : 1][NT];
-        if constexpr (kBitsOnce) {
+        F bits[KBN1_USED][NT];
 #pragma unroll
-            for (int kb = 0; kb < KBN1_USED; ++kb)
+        for (int kb = 0; kb < KBN1_USED; ++kb)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) bits[kb][nt] = Bits<PREC>::get(hv[nt], kb, g, stab);
-        }
+            for (int nt = 0; nt < NT; ++nt) bits[kb][nt] = Bits<PREC>::get(hv[nt], kb, g, stab);
         if constexpr (!(LDSM & 1)) {
 #pragma unroll
             for (int kb = 0; kb < KBN1_USED; ++kb) pre[kb] = ldf<false>(s1, r1, kb, lane, sbase);
@@ -321,14 +351,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
 #pragma unroll
             for (int kb = 0; kb < KBN1_USED; ++kb) {
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    if constexpr (kBitsOnce) acc[nt] = mma(cur[kb], bits[kb][nt], acc[nt]);
-                    else acc[nt] = mma(cur[kb], Bits<PREC>::get(hv[nt], kb, g), acc[nt]);
-                }
+                for (int nt = 0; nt < NT; ++nt) acc[nt] = mma(cur[kb], bits[kb][nt], acc[nt]);
             }
             epi_hidden<PREC, NT, KBNH>(acc, mt, sb, a.hs[0], g, a0);
             // keep the scheduler from hoisting every tile's fragment loads (register blow-up)
             __builtin_amdgcn_sched_barrier(0);
+        }
         }
         // layer 2: H -> H, TG output tiles per group: all MFMAs of the group are issued
         // before its epilogues, so the matrix pipe has independent work while results land
@@ -508,6 +536,8 @@ void model_free(ModelDev& m) {
     }
     if (m.bias) hipFree(m.bias);
     m.bias = nullptr;
+    if (m.w1x3) hipFree(m.w1x3);
+    m.w1x3 = nullptr;
     if (m.rin) hipFree(m.rin);
     if (m.rw) hipFree(m.rw);
     if (m.ws) hipFree(m.ws);
@@ -598,6 +628,38 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
         m.wbytes[l] = buf.size();
         m.bytes += buf.size();
     }
+    if (p == TANG_FP32) {
+        // W1 as three BF16 planes in BF16 layer-0 fragment order: hi = w cut to BF16
+        // (low 16 bits dropped), mid = (w - hi) cut likewise, lo = w - hi - mid. Each
+        // difference is exact in FP32 and lo keeps at most 8 significant bits, so
+        // hi + mid + lo = w exactly; cutting (not rounding) never overflows to infinity.
+        const int MT = H / 16;
+        std::vector<uint16_t> x3((size_t)MT * 4 * 3 * 64 * 8, 0);
+        for (int mt = 0; mt < MT; ++mt)
+            for (int kb = 0; kb < 4; ++kb)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int j = 0; j < 8; ++j) {
+                        const int row = 16 * mt + (lane & 15), c = in_col(TANG_BF16, 0, kb, lane >> 4, j);
+                        const float w = c < 104 ? W[0][(size_t)row * 104 + c] : 0.0f;
+                        uint16_t q[3];
+                        float rest = w;
+                        for (int pl = 0; pl < 3; ++pl) {
+                            uint32_t u;
+                            std::memcpy(&u, &rest, 4);
+                            q[pl] = (uint16_t)(u >> 16);
+                            u &= 0xFFFF0000u;
+                            float back;
+                            std::memcpy(&back, &u, 4);
+                            rest -= back;
+                        }
+                        for (int pl = 0; pl < 3; ++pl)
+                            x3[((((size_t)mt * 4 + kb) * 3 + pl) * 64 + lane) * 8 + j] = q[pl];
+                    }
+        hipError_t e = hipMalloc(&m.w1x3, x3.size() * 2);
+        if (e == hipSuccess) e = hipMemcpy(m.w1x3, x3.data(), x3.size() * 2, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { model_free(m); return hip_fail(e, "model upload"); }
+        m.bytes += x3.size() * 2;
+    }
     // FP8 hidden biases are stored prescaled by the next layer's inverse activation scale
     std::vector<float> bias(2 * H + CP, 0.0f);
     for (int k = 0; k < H; ++k) {
@@ -627,7 +689,7 @@ hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, u
                      n3 = 2 * (H / KB) * 64;
     const size_t lds = ((LDSM & 1) ? n1 : 0) * sizeof(F) + ((LDSM & 2) ? n2 : 0) * sizeof(F) +
                        ((LDSM & 4) ? n3 : 0) * sizeof(F) + (2 * H + kOutPad * OUTB) * sizeof(float) +
-                       (PREC == TANG_BF16 ? 256 * 16 : PREC == TANG_FP8 ? 256 * 8 : 0);
+                       (PREC == TANG_FP8 ? 256 * 8 : 256 * 16);  // bit table (BF16's for FP32)
     auto kern = k_mlp<PREC, H, NT, LDSM, WAVES, OUTB>;
     static int attr_done = 0;  // per instantiation
     if (!attr_done) {
@@ -655,7 +717,7 @@ hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, u
     for (int l = 0; l < 2; ++l) a.hs[l] = m.deq[l] * m.inv_a[l + 1];
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WAVES), lds, s,
                        reinterpret_cast<const uint4*>(d_hdr), n, (const F*)m.w[0], (const F*)m.w[1],
-                       (const F*)m.w[2], m.bias, a, cand, logits, cand8);
+                       (const F*)m.w[2], (const u32x4*)m.w1x3, m.bias, a, cand, logits, cand8);
     return hipGetLastError();
 }
 
@@ -674,19 +736,20 @@ hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size
         uint8_t* c8 = d_cand8 ? d_cand8 + base * (size_t)m.topk : nullptr;
         hipError_t e;
         // LDSM: which layers' fragments sit in LDS (bit l = layer l) -- 160 KB per CU.
+        // FP32 reads its input layer's BF16 planes from L2 (bit 0 unused).
         // H = 256 runs 8 waves per CU (2 per SIMD): fewer than the register file would
         // hold, so that a chunked classify's search waves fit beside them.
         // More than 32 tuples: up to 8 blocks of 32 classes, W3 read from L2.
         const bool wide = m.n_out > kOutPad;
         if (wide) {
-            if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 3, 8, 8>(m, h, k, c, lg, c8, s);
+            if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 2, 8, 8>(m, h, k, c, lg, c8, s);
             else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0, 8, 8>(m, h, k, c, lg, c8, s);
             else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 3, 8, 8>(m, h, k, c, lg, c8, s);
             else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 2, 8, 8>(m, h, k, c, lg, c8, s);
             else if (m.hidden == 128) e = launch_t<TANG_FP8, 128, 2, 3, 8, 8>(m, h, k, c, lg, c8, s);
             else e = launch_t<TANG_FP8, 256, 2, 3, 8, 8>(m, h, k, c, lg, c8, s);
         }
-        else if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 7>(m, h, k, c, lg, c8, s);
+        else if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 6>(m, h, k, c, lg, c8, s);
         else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0>(m, h, k, c, lg, c8, s);
         else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 7>(m, h, k, c, lg, c8, s);
         else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 6, 8>(m, h, k, c, lg, c8, s);

@@ -179,6 +179,9 @@ struct ModelDev {
     // Weight fragments for the three layers in MFMA A-operand order, and biases.
     void* w[3] = {nullptr, nullptr, nullptr};
     size_t wbytes[3] = {0, 0, 0};
+    // FP32 models: W1 as three BF16 planes (hi + mid + lo = W1 exactly) in BF16 fragment
+    // order, for the input layer on BF16 MFMAs (its inputs are bits, so products are exact)
+    void* w1x3 = nullptr;
     float* bias = nullptr;   // [hidden | hidden | 32] floats
     float deq[3] = {1, 1, 1};     // FP8: s_a * s_w per layer
     float inv_a[3] = {1, 1, 1};   // FP8: 1 / s_a per layer (layer 0 unused)
