@@ -186,6 +186,15 @@ def main():
             top1_hit_rate=st["top1_hits"] / n, fallback_rate=st["fallbacks"] / n,
             filter_checks_per_pkt=F, wave_steps=st["wave_steps"] / n,
             wave_rounds=st["wave_rounds"] / n, search_bytes_per_pkt=bytes_pkt)
+        # stage rooflines in Mpps: the predictor at its MFMA peak, the search at HBM peak
+        # over its algorithmic bytes; serial = both back to back, overlap = the slower one
+        k1_mpps = PEAK_TFLOPS[prec] * 1e12 / flop_pkt / 1e6
+        k2_mpps = PEAK_HBM_GBS * 1e9 / bytes_pkt / 1e6
+        serial = 1.0 / (1.0 / k1_mpps + 1.0 / k2_mpps)
+        per[prec]["roofline_mpps"] = dict(k_mlp=k1_mpps, k_classify=k2_mpps, serial=serial,
+                                          overlapped=min(k1_mpps, k2_mpps),
+                                          frac_of_serial=per[prec]["mpps"] / serial,
+                                          frac_of_overlapped=per[prec]["mpps"] / min(k1_mpps, k2_mpps))
         log(f"[bench] {prec}: {per[prec]['mpps']:.0f} Mpps, mlp {k1:.3f} ms, search {k23:.3f} ms, "
             f"probes/pkt {per[prec]['probes_per_pkt']:.2f}, filter checks/pkt {F:.2f}, "
             f"wave filter batches {per[prec]['wave_rounds']:.2f}, wave probe steps {per[prec]['wave_steps']:.2f}")
