@@ -123,3 +123,34 @@ def test_wide_updates_and_appended_tuples():
             assert m & need == need, (k, hex(m), hex(need))
     finally:
         T.tang_ruleset_destroy(rs)
+
+
+def test_wide_chunked_classify():
+    """A 144-tuple ruleset through the chunked classify (two 2^21-header chunks and a
+    ragged third, each chunk's search on the ruleset's stream behind the next chunk's
+    model): every answer equals the oracle's, with a trained and with a random model,
+    BF16 top-1 and FP8 top-2."""
+    torch = torch_cuda()
+    rules = synth.make_rules(20_000, seed=78, wide=True)
+    hdr = synth.make_packets(rules, 100_000, seed=79, frac_in=0.8)
+    want = orc.classify(rules, hdr)
+    n = 2 * (1 << 21) + 333
+    reps = (n + len(hdr) - 1) // len(hdr)
+    big = np.concatenate([hdr] * reps)[:n]
+    big_want = np.concatenate([want] * reps)[:n]
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        C = T.tang_ruleset_num_tuples(rs)
+        Ws, bs, sc, acc = train.fit(rs, rules, hdr[:50_000], 256, steps=300, seed=4,
+                                    rule_ids=want[:50_000], device="cuda")
+        d_hdr = torch.from_numpy(big.view(np.uint8).reshape(-1).copy()).cuda()
+        d_out = torch.empty(n, dtype=torch.int32, device="cuda")
+        for name, (W, b) in {"trained": (Ws, bs), "random": train.random_weights(C, 256, seed=6)}.items():
+            for prec, k in (("bf16", 1), ("fp8", 2)):
+                T.tang_model_load(rs, W, b, prec, topk=k, act_scales=sc if prec == "fp8" else None)
+                d_out.fill_(-7)
+                T.tang_classify(rs, d_hdr, d_out, n, torch.cuda.current_stream())
+                torch.cuda.synchronize()
+                assert np.array_equal(d_out.cpu().numpy().view(np.uint32), big_want), (name, prec)
+    finally:
+        T.tang_ruleset_destroy(rs)
