@@ -20,7 +20,8 @@
  *   - A stream argument is a hipStream_t passed as void* (NULL = the null stream).
  *   - Input arrays are deep-copied; the caller keeps ownership of everything it passes.
  *   - The library owns only its internal device memory (hipMalloc'd on the ruleset's
- *     device, freed by tang_ruleset_destroy).
+ *     device, or taken from the caller's allocator, see tang_set_allocator; freed by
+ *     tang_ruleset_destroy, model reloads and server destruction).
  */
 #ifndef TANG_H
 #define TANG_H
@@ -265,6 +266,23 @@ int tang_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n);
 
 /* Message for the calling thread's last error ("" if none). */
 const char* tang_last_error(void);
+
+/*
+ * Optional allocator for the library's internal device memory (tables, records, conflict
+ * masks, model weights and workspaces, staging buffers, server slots), so that a caller's
+ * pool (for example torch's caching allocator) can own it. alloc(bytes, device, ctx)
+ * returns memory on HIP device `device` (the current device at the call), aligned to at
+ * least 256 bytes, or NULL (the library then fails with TANG_ENOMEM); free(ptr, device,
+ * ctx) returns it. Process-wide; alloc == NULL restores hipMalloc / hipFree. Each block
+ * is returned through the allocator that provided it, even after a change, and only
+ * after the device has finished its queued work (as hipFree would). The
+ * callbacks may be called from any thread that calls into the library (and from the
+ * serving loop's threads); they must not call back into it. Errors: EINVAL (exactly one
+ * of alloc and free is NULL).
+ */
+typedef void* (*tang_alloc_fn)(size_t bytes, int device, void* ctx);
+typedef void (*tang_free_fn)(void* ptr, int device, void* ctx);
+int tang_set_allocator(tang_alloc_fn alloc, tang_free_fn free_fn, void* ctx);
 
 /* ------------------------------------------------------------------------------------
  * Serving loop: continuous batching over several device-resident rulesets.

@@ -1,12 +1,75 @@
 // C ABI entry points (include/tang.h): argument checks, error codes, and the calls
 // into the host tuple space and the kernels. No C++ exception crosses this boundary.
+#include <mutex>
 #include <new>
+#include <unordered_map>
 
 #include "tang_internal.hpp"
 
 namespace tang {
 
 static thread_local std::string g_err;
+
+// The caller's allocator (tang_set_allocator) and, per block it provided, the free
+// callback to return it through.
+namespace {
+struct Allocator {
+    tang_alloc_fn alloc = nullptr;
+    tang_free_fn free = nullptr;
+    void* ctx = nullptr;
+};
+struct Owner {
+    tang_free_fn free;
+    void* ctx;
+    int device;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+std::unordered_map<void*, Owner> g_owned;
+}  // namespace
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    Allocator a;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        a = g_alloc;
+    }
+    if (!a.alloc) return hipMalloc(p, bytes);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    void* q = a.alloc(bytes, dev, a.ctx);
+    if (!q) return hipErrorOutOfMemory;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_owned[q] = Owner{a.free, a.ctx, dev};
+    *p = q;
+    return hipSuccess;
+}
+
+hipError_t dev_release(void* p) {
+    if (!p) return hipSuccess;
+    Owner o{nullptr, nullptr, 0};
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        auto it = g_owned.find(p);
+        if (it != g_owned.end()) {
+            o = it->second;
+            g_owned.erase(it);
+        }
+    }
+    if (!o.free) return hipFree(p);
+    // hipFree waits for the device's work; so does a release through the caller's
+    // allocator, since the block may still be read by kernels in flight on the
+    // library's own streams, which the caller's allocator knows nothing about
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != o.device) e = hipSetDevice(o.device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (cur != o.device) (void)hipSetDevice(cur);
+    o.free(p, o.device, o.ctx);
+    return e;
+}
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -47,14 +110,14 @@ static void free_device(tang_ruleset_t* rs) {
     if (rs->device == TANG_HOST_ONLY) return;
     hipSetDevice(rs->device);
     model_free(rs->model);
-    if (rs->d_slots) hipFree(rs->d_slots);
-    if (rs->d_filter) hipFree(rs->d_filter);
+    if (rs->d_slots) dev_release(rs->d_slots);
+    if (rs->d_filter) dev_release(rs->d_filter);
     rs->d_filter = nullptr;
-    if (rs->d_recs) hipFree(rs->d_recs);
-    if (rs->d_cmask) hipFree(rs->d_cmask);
+    if (rs->d_recs) dev_release(rs->d_recs);
+    if (rs->d_cmask) dev_release(rs->d_cmask);
     rs->d_cmask = nullptr;
-    if (rs->d_tt) hipFree(rs->d_tt);
-    if (rs->d_stats) hipFree(rs->d_stats);
+    if (rs->d_tt) dev_release(rs->d_tt);
+    if (rs->d_stats) dev_release(rs->d_stats);
     for (hipEvent_t e : rs->pipe_events) hipEventDestroy(e);
     rs->pipe_events.clear();
     if (rs->pipe_stream) hipStreamDestroy(rs->pipe_stream);
@@ -66,6 +129,14 @@ static void free_device(tang_ruleset_t* rs) {
 }
 
 extern "C" {
+
+int tang_set_allocator(tang_alloc_fn alloc, tang_free_fn free_fn, void* ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(TANG_EINVAL, "set both allocator callbacks, or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = Allocator{alloc, free_fn, alloc ? ctx : nullptr};
+    return TANG_OK;
+}
 
 const char* tang_last_error(void) { return tang::g_err.c_str(); }
 
@@ -375,16 +446,16 @@ int tang_classify_host(tang_ruleset_t* rs, const tang_header_t* hdr, uint32_t* r
     TANG_HIP(hipSetDevice(rs->device));
     tang_header_t* dh = nullptr;
     uint32_t* dout = nullptr;
-    TANG_HIP(hipMalloc(&dh, n * sizeof(tang_header_t)));
-    hipError_t e = hipMalloc(&dout, n * sizeof(uint32_t));
+    TANG_HIP(dev_alloc(&dh, n * sizeof(tang_header_t)));
+    hipError_t e = dev_alloc(&dout, n * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemcpy(dh, hdr, n * sizeof(tang_header_t), hipMemcpyHostToDevice);
     int rc = TANG_OK;
     if (e == hipSuccess) {
         rc = tang_classify(rs, dh, dout, n, nullptr, stats);
         if (rc == TANG_OK) e = hipMemcpy(rule_id, dout, n * sizeof(uint32_t), hipMemcpyDeviceToHost);
     }
-    hipFree(dh);
-    if (dout) hipFree(dout);
+    dev_release(dh);
+    if (dout) dev_release(dout);
     if (e != hipSuccess) return hip_fail(e, "tang_classify_host");
     return rc;
     TANG_GUARD_END

@@ -13,6 +13,9 @@
 // one dependent L2 round trip per tuple would cost two dozen round trips back to back,
 // and a wave-uniform loop over tuples would pay for the union of all lanes' tuples.
 // Candidates come packed in the output word (one byte per candidate) from the MLP.
+// Tuple spaces of more than 32 tuples (up to 256) use the same steps over eight-word
+// tuple masks, with conflict masks in a side array, a pre-check of the header's field
+// keys before the filter sweep, and per-lane filter batches.
 #include "tang_internal.hpp"
 
 namespace tang {

@@ -531,16 +531,16 @@ int in_col(int prec, int layer, int kb, int g, int j) {
 
 void model_free(ModelDev& m) {
     for (auto& p : m.w) {
-        if (p) hipFree(p);
+        if (p) dev_release(p);
         p = nullptr;
     }
-    if (m.bias) hipFree(m.bias);
+    if (m.bias) dev_release(m.bias);
     m.bias = nullptr;
-    if (m.w1x3) hipFree(m.w1x3);
+    if (m.w1x3) dev_release(m.w1x3);
     m.w1x3 = nullptr;
-    if (m.rin) hipFree(m.rin);
-    if (m.rw) hipFree(m.rw);
-    if (m.ws) hipFree(m.ws);
+    if (m.rin) dev_release(m.rin);
+    if (m.rw) dev_release(m.rw);
+    if (m.ws) dev_release(m.ws);
     if (m.ws_done) hipEventDestroy(m.ws_done);
     m.rin = nullptr;
     m.rw = nullptr;
@@ -622,7 +622,7 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
                             buf[at] = f32_to_e4m3(w * inv_w);
                         }
                     }
-        hipError_t e = hipMalloc(&m.w[l], buf.size());
+        hipError_t e = dev_alloc(&m.w[l], buf.size());
         if (e == hipSuccess) e = hipMemcpy(m.w[l], buf.data(), buf.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) { model_free(m); return hip_fail(e, "model upload"); }
         m.wbytes[l] = buf.size();
@@ -655,7 +655,7 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
                         for (int pl = 0; pl < 3; ++pl)
                             x3[((((size_t)mt * 4 + kb) * 3 + pl) * 64 + lane) * 8 + j] = q[pl];
                     }
-        hipError_t e = hipMalloc(&m.w1x3, x3.size() * 2);
+        hipError_t e = dev_alloc(&m.w1x3, x3.size() * 2);
         if (e == hipSuccess) e = hipMemcpy(m.w1x3, x3.data(), x3.size() * 2, hipMemcpyHostToDevice);
         if (e != hipSuccess) { model_free(m); return hip_fail(e, "model upload"); }
         m.bytes += x3.size() * 2;
@@ -667,7 +667,7 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
         bias[H + k] = p == TANG_FP8 ? b[1][k] * m.inv_a[2] : b[1][k];
     }
     for (int k = 0; k < C; ++k) bias[2 * H + k] = b[2][k];
-    hipError_t e = hipMalloc(&m.bias, bias.size() * 4);
+    hipError_t e = dev_alloc(&m.bias, bias.size() * 4);
     if (e == hipSuccess) e = hipMemcpy(m.bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice);
     if (e != hipSuccess) { model_free(m); return hip_fail(e, "bias upload"); }
     m.bytes += bias.size() * 4;

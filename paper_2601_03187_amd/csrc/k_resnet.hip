@@ -373,13 +373,13 @@ int resnet_prepare(tang_ruleset_t* rs, const tang_resnet_desc_t* d, const float*
         for (int k = 0; k < kW; ++k)
             w[(size_t)2 * nb * kW * kW + (size_t)c * kW + k] = to_bf16(W[L - 1][(size_t)c * kW + k]);
 
-    hipError_t e = hipMalloc(&m.rin, win.size() * 4);
+    hipError_t e = dev_alloc(&m.rin, win.size() * 4);
     if (e == hipSuccess) e = hipMemcpy(m.rin, win.data(), win.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&m.bias, bias.size() * 4);
+    if (e == hipSuccess) e = dev_alloc(&m.bias, bias.size() * 4);
     if (e == hipSuccess) e = hipMemcpy(m.bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&m.rw, w.size() * 2);
+    if (e == hipSuccess) e = dev_alloc(&m.rw, w.size() * 2);
     if (e == hipSuccess) e = hipMemcpy(m.rw, w.data(), w.size() * 2, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&m.ws, (size_t)3 * kChunk * kW * 2);
+    if (e == hipSuccess) e = dev_alloc(&m.ws, (size_t)3 * kChunk * kW * 2);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&m.ws_done, hipEventDisableTiming);
     if (e != hipSuccess) {
         model_free(m);

@@ -253,8 +253,8 @@ static void free_server(tang_server_t* srv) {
         if (s.stream) hipStreamDestroy(s.stream);
         if (s.h_hdr) hipHostFree(s.h_hdr);
         if (s.h_out) hipHostFree(s.h_out);
-        if (s.d_hdr) hipFree(s.d_hdr);
-        if (s.d_out) hipFree(s.d_out);
+        if (s.d_hdr) dev_release(s.d_hdr);
+        if (s.d_out) dev_release(s.d_out);
     }
     delete srv;
 }
@@ -289,8 +289,8 @@ int tang_server_create(int device, const tang_server_cfg_t* cfg, tang_server_t**
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
             if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_hdr, c.max_batch * sizeof(tang_header_t), 0);
             if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_out, c.max_batch * sizeof(uint32_t), 0);
-            if (e == hipSuccess) e = hipMalloc(&s.d_hdr, c.max_batch * sizeof(tang_header_t));
-            if (e == hipSuccess) e = hipMalloc(&s.d_out, c.max_batch * sizeof(uint32_t));
+            if (e == hipSuccess) e = dev_alloc(&s.d_hdr, c.max_batch * sizeof(tang_header_t));
+            if (e == hipSuccess) e = dev_alloc(&s.d_out, c.max_batch * sizeof(uint32_t));
             if (e == hipSuccess) e = hipMemset(s.d_hdr, 0, c.max_batch * sizeof(tang_header_t));
         }
         if (e != hipSuccess) {

@@ -283,6 +283,16 @@ Rec make_rec(const tang_ruleset_t* rs, uint32_t h);
 int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n);
 int apply_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n);
 
+// Internal device memory: through the caller's allocator when one is set
+// (tang_set_allocator), else hipMalloc / hipFree; a block is released through the
+// allocator that provided it.
+hipError_t dev_alloc(void** p, size_t bytes);
+hipError_t dev_release(void* p);
+template <class T>
+inline hipError_t dev_alloc(T** p, size_t bytes) {
+    return dev_alloc(reinterpret_cast<void**>(p), bytes);
+}
+
 // Kernel launchers (k_classify.hip, k_build.hip, k_mlp.hip).
 hipError_t launch_classify(const tang_ruleset_t* rs, const tang_header_t* d_hdr,
                            uint32_t* d_out, size_t n, int kcand, hipStream_t s, bool stats);

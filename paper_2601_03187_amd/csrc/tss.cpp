@@ -267,17 +267,17 @@ int build_host(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
 int upload_all(tang_ruleset_t* rs) {
     TANG_HIP(hipSetDevice(rs->device));
     hipStream_t s = rs->upd_stream;
-    TANG_HIP(hipMalloc(&rs->d_slots, rs->slots.size() * sizeof(Slot)));
-    TANG_HIP(hipMalloc(&rs->d_filter, rs->filter.size() * sizeof(uint32_t)));
+    TANG_HIP(dev_alloc(&rs->d_slots, rs->slots.size() * sizeof(Slot)));
+    TANG_HIP(dev_alloc(&rs->d_filter, rs->filter.size() * sizeof(uint32_t)));
     TANG_HIP(hipMemcpy(rs->d_filter, rs->filter.data(), rs->filter.size() * sizeof(uint32_t),
                        hipMemcpyHostToDevice));
-    TANG_HIP(hipMalloc(&rs->d_recs, (size_t)rs->rec_cap * sizeof(Rec)));
+    TANG_HIP(dev_alloc(&rs->d_recs, (size_t)rs->rec_cap * sizeof(Rec)));
     if (rs->nw > 1) {
-        TANG_HIP(hipMalloc(&rs->d_cmask, (size_t)rs->rec_cap * kMaskWords * sizeof(uint32_t)));
+        TANG_HIP(dev_alloc(&rs->d_cmask, (size_t)rs->rec_cap * kMaskWords * sizeof(uint32_t)));
         TANG_HIP(hipMemset(rs->d_cmask, 0, (size_t)rs->rec_cap * kMaskWords * sizeof(uint32_t)));
     }
-    TANG_HIP(hipMalloc(&rs->d_tt, sizeof(TupleTable)));
-    TANG_HIP(hipMalloc(&rs->d_stats, kStatCopies * sizeof(StatsDev)));
+    TANG_HIP(dev_alloc(&rs->d_tt, sizeof(TupleTable)));
+    TANG_HIP(dev_alloc(&rs->d_stats, kStatCopies * sizeof(StatsDev)));
 
     std::vector<Rec> recs(rs->rec_cap, dead_rec());
     for (uint32_t h = 0; h < rs->rules.size(); ++h)
@@ -309,14 +309,14 @@ int upload_all(tang_ruleset_t* rs) {
                               hr.pos};
         }
         BoxDev* d_boxes = nullptr;
-        TANG_HIP(hipMalloc(&d_boxes, boxes.size() * sizeof(BoxDev)));
+        TANG_HIP(dev_alloc(&d_boxes, boxes.size() * sizeof(BoxDev)));
         hipError_t e = hipMemcpy(d_boxes, boxes.data(), boxes.size() * sizeof(BoxDev),
                                  hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = launch_conflict_build(d_boxes, boxes.size(), rs->d_recs, rs->d_cmask, rs->nw,
                                       rs->d_tt->all_mask, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        hipFree(d_boxes);
+        dev_release(d_boxes);
         if (e != hipSuccess) return hip_fail(e, "conflict-mask build");
     }
     return TANG_OK;
@@ -355,7 +355,7 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
     if (need_end > rs->rec_cap) {
         uint32_t ncap = std::max<uint32_t>(need_end + need_end / 2, rs->rec_cap * 2);
         Rec* nrec = nullptr;
-        TANG_HIP(hipMalloc(&nrec, (size_t)ncap * sizeof(Rec)));
+        TANG_HIP(dev_alloc(&nrec, (size_t)ncap * sizeof(Rec)));
         TANG_HIP(hipMemcpyAsync(nrec, rs->d_recs, (size_t)rs->rec_used * sizeof(Rec),
                                 hipMemcpyDeviceToDevice, s));
         std::vector<Rec> tail(ncap - rs->rec_used, dead_rec());
@@ -364,16 +364,16 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
         if (rs->nw > 1) {
             uint32_t* nmask = nullptr;
             const size_t row = kMaskWords * sizeof(uint32_t);
-            TANG_HIP(hipMalloc(&nmask, (size_t)ncap * row));
+            TANG_HIP(dev_alloc(&nmask, (size_t)ncap * row));
             TANG_HIP(hipMemsetAsync(nmask, 0, (size_t)ncap * row, s));
             TANG_HIP(hipMemcpyAsync(nmask, rs->d_cmask, (size_t)rs->rec_used * row,
                                     hipMemcpyDeviceToDevice, s));
             TANG_HIP(hipStreamSynchronize(s));
-            TANG_HIP(hipFree(rs->d_cmask));
+            TANG_HIP(dev_release(rs->d_cmask));
             rs->d_cmask = nmask;
         }
         TANG_HIP(hipStreamSynchronize(s));
-        TANG_HIP(hipFree(rs->d_recs));
+        TANG_HIP(dev_release(rs->d_recs));
         rs->d_recs = nrec;
         rs->rec_cap = ncap;
     }
@@ -420,7 +420,7 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
     auto dev_copy = [&](const void* host, size_t bytes, void** out) -> hipError_t {
         *out = nullptr;
         if (!bytes) return hipSuccess;
-        hipError_t e = hipMalloc(out, bytes);
+        hipError_t e = dev_alloc(out, bytes);
         if (e != hipSuccess) return e;
         tmp.push_back(*out);
         return hipMemcpyAsync(*out, host, bytes, hipMemcpyHostToDevice, s);
@@ -433,7 +433,7 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
         if (e == hipSuccess && !newrecs.empty())
             e = dev_copy(newrecs.data(), newrecs.size() * sizeof(Rec), &d_new);
         if (e == hipSuccess) {
-            e = hipMalloc(&d_stage, dst.size() * sizeof(Rec));
+            e = dev_alloc(&d_stage, dst.size() * sizeof(Rec));
             if (e == hipSuccess) tmp.push_back(d_stage);
         }
         if (e == hipSuccess)
@@ -441,7 +441,7 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
                                     (const uint32_t*)d_dst, (uint32_t)dst.size(), (Rec*)d_stage, s);
         if (e == hipSuccess && rs->nw > 1) {
             void* d_mstage = nullptr;
-            e = hipMalloc(&d_mstage, dst.size() * kMaskWords * sizeof(uint32_t));
+            e = dev_alloc(&d_mstage, dst.size() * kMaskWords * sizeof(uint32_t));
             if (e == hipSuccess) {
                 tmp.push_back(d_mstage);
                 e = launch_move_masks(rs->d_cmask, (const uint32_t*)d_src, (const uint32_t*)d_dst,
@@ -455,8 +455,8 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
             Slot* ns = nullptr;
             uint32_t* nf = nullptr;
             e = hipStreamSynchronize(s);
-            if (e == hipSuccess) e = hipMalloc(&ns, rs->slots.size() * sizeof(Slot));
-            if (e == hipSuccess) e = hipMalloc(&nf, rs->filter.size() * sizeof(uint32_t));
+            if (e == hipSuccess) e = dev_alloc(&ns, rs->slots.size() * sizeof(Slot));
+            if (e == hipSuccess) e = dev_alloc(&nf, rs->filter.size() * sizeof(uint32_t));
             if (e == hipSuccess)
                 e = hipMemcpyAsync(ns, rs->slots.data(), rs->slots.size() * sizeof(Slot),
                                    hipMemcpyHostToDevice, s);
@@ -465,13 +465,13 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
                                    hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e == hipSuccess) {
-                hipFree(rs->d_slots);
-                hipFree(rs->d_filter);
+                dev_release(rs->d_slots);
+                dev_release(rs->d_filter);
                 rs->d_slots = ns;
                 rs->d_filter = nf;
             } else {
-                if (ns) hipFree(ns);
-                if (nf) hipFree(nf);
+                if (ns) dev_release(ns);
+                if (nf) dev_release(nf);
             }
         } else if (!touched_slots.empty()) {
             std::sort(touched_slots.begin(), touched_slots.end());
@@ -503,7 +503,7 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
                                        (const uint32_t*)d_pos, (uint32_t)pos.size(), s);
     }
     hipError_t e2 = hipStreamSynchronize(s);
-    for (void* p : tmp) hipFree(p);
+    for (void* p : tmp) dev_release(p);
     if (e != hipSuccess) return hip_fail(e, "update flush");
     if (e2 != hipSuccess) return hip_fail(e2, "update flush sync");
     return TANG_OK;

@@ -71,7 +71,11 @@ except ImportError:  # pragma: no cover - torch is only plumbing for device buff
 _lib = ctypes.CDLL(LIB_PATH)
 
 _P = ctypes.c_void_p
+# tang_alloc_fn / tang_free_fn
+ALLOC_FN = ctypes.CFUNCTYPE(_P, ctypes.c_size_t, ctypes.c_int, _P)
+FREE_FN = ctypes.CFUNCTYPE(None, _P, ctypes.c_int, _P)
 _sigs = {
+    "tang_set_allocator": (ctypes.c_int, [ALLOC_FN, FREE_FN, _P]),
     "tang_ruleset_create": (ctypes.c_int, [ctypes.c_int, _P, ctypes.c_size_t, ctypes.POINTER(_P)]),
     "tang_ruleset_destroy": (None, [_P]),
     "tang_ruleset_num_tuples": (ctypes.c_uint32, [_P]),
@@ -317,6 +321,42 @@ def tang_insert(rs: int, rules) -> None:
 def tang_delete(rs: int, ids) -> None:
     a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
     _check(_lib.tang_delete(rs, a.ctypes.data if len(a) else None, len(a)))
+
+
+_allocator_refs = None  # the ctypes callbacks in use (kept alive while installed)
+
+
+def tang_set_allocator(alloc=None, free=None) -> None:
+    """Route the library's internal device memory through alloc(bytes, device) -> int
+    pointer (0 on failure) and free(ptr, device); tang_set_allocator() restores hipMalloc."""
+    global _allocator_refs
+    if alloc is None and free is None:
+        _check(_lib.tang_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+    if alloc is None or free is None:
+        _check(_lib.tang_set_allocator(ALLOC_FN(alloc) if alloc else ALLOC_FN(),
+                                       FREE_FN(free) if free else FREE_FN(), None))
+        return
+    a = ALLOC_FN(lambda nbytes, dev, ctx: alloc(nbytes, dev) or None)
+    f = FREE_FN(lambda ptr, dev, ctx: free(ptr, dev))
+    _check(_lib.tang_set_allocator(a, f, None))
+    _allocator_refs = (a, f)
+
+
+def torch_allocator():
+    """(alloc, free) over torch's caching allocator, for tang_set_allocator."""
+    import torch
+
+    def alloc(nbytes, dev):
+        try:
+            return torch.cuda.caching_allocator_alloc(max(int(nbytes), 1), device=dev)
+        except RuntimeError:
+            return 0
+
+    def free(ptr, dev):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, free
 
 
 def tang_last_error() -> str:

@@ -246,3 +246,12 @@ def test_export_returns_live_rules_in_priority_order():
         T.tang_ruleset_destroy(rs2)
     finally:
         T.tang_ruleset_destroy(rs)
+
+
+def test_allocator_callbacks_come_in_pairs():
+    """tang_set_allocator: one callback without the other is EINVAL; none restores the
+    default (no device is touched by either call)."""
+    with pytest.raises(T.TangError) as e:
+        T.tang_set_allocator(lambda n, d: 0, None)
+    assert e.value.name == "EINVAL"
+    T.tang_set_allocator()

@@ -1,0 +1,67 @@
+"""The library's internal device memory through a caller's allocator (tang_set_allocator),
+here torch's caching allocator: every block the library takes is returned, and the
+answers are the oracle's, through a build, a model load, updates that grow the record
+array and the slot table, and the residual model's workspace."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2601_03187_amd import synth, train
+from paper_2601_03187_amd import tang as T
+from tests._gpu import classify_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def test_internal_memory_through_callers_allocator():
+    torch_cuda()
+    live, calls = {}, {"alloc": 0, "free": 0}
+    talloc, tfree = T.torch_allocator()
+
+    def alloc(nbytes, dev):
+        p = talloc(nbytes, dev)
+        if p:
+            calls["alloc"] += 1
+            live[p] = nbytes
+        return p
+
+    def free(p, dev):
+        calls["free"] += 1
+        assert live.pop(p, None) is not None, hex(p)
+        tfree(p, dev)
+
+    T.tang_set_allocator(alloc, free)
+    try:
+        rules = synth.make_rules(5_000, seed=81)
+        rs = T.tang_ruleset_create(0, rules)
+        try:
+            assert calls["alloc"] >= 5 and all(p % 256 == 0 for p in live)
+            C = T.tang_ruleset_num_tuples(rs)
+            T.tang_model_load(rs, *train.random_weights(C, 256, seed=3), "bf16", topk=2)
+            hdr = synth.make_packets(rules, 50_000, seed=82, frac_in=0.8)
+            assert np.array_equal(classify_dev(rs, hdr), orc.classify(rules, hdr))
+            # enough fresh rules to grow the record array and rebuild the slot table
+            ins = synth.make_rules(40_000, seed=83)
+            ins["id"] += 1_000_000
+            before = calls["alloc"]
+            T.tang_insert(rs, ins)
+            T.tang_delete(rs, rules["id"][::3])
+            assert calls["alloc"] > before
+            every = np.concatenate([rules, ins])
+            lm = ~np.isin(every["id"], rules["id"][::3])
+            pk = synth.make_packets(every[lm], 50_000, seed=84, frac_in=0.8)
+            assert np.array_equal(classify_dev(rs, pk), orc.classify(every, pk, live=lm))
+            rng = np.random.default_rng(5)
+            Wr = [rng.normal(0, 2.0, (512, 7))] + [rng.normal(0, 1 / np.sqrt(512), (512, 512)) for _ in range(2)]
+            Wr.append(rng.normal(0, 1 / np.sqrt(512), (C, 512)))
+            br = [rng.normal(0, 0.05, w.shape[0]) for w in Wr]
+            T.tang_model_load_resnet(rs, [w.astype(np.float32) for w in Wr],
+                                     [b.astype(np.float32) for b in br], "bf16")
+            assert max(live.values()) >= 3 * 65536 * 512 * 2  # the workspace came from torch
+            assert np.array_equal(classify_dev(rs, pk), orc.classify(every, pk, live=lm))
+        finally:
+            T.tang_ruleset_destroy(rs)
+        assert not live, f"{len(live)} blocks not returned"
+        assert calls["free"] == calls["alloc"]
+    finally:
+        T.tang_set_allocator()
