@@ -357,7 +357,7 @@ static int classify_chunked(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint
     const int kcand = rs->model.topk;
     for (size_t k = 0; k < K; ++k) {
         const size_t base = k * kPipeChunk, m = std::min(kPipeChunk, n - base);
-        TANG_HIP(launch_mlp(rs, d_hdr + base, m, out + base, nullptr, nullptr, s));
+        TANG_HIP(launch_mlp(rs, d_hdr + base, m, out + base, nullptr, nullptr, s, true));
         TANG_HIP(hipEventRecord(rs->pipe_events[k], s));
         TANG_HIP(hipStreamWaitEvent(rs->pipe_stream, rs->pipe_events[k], 0));
         TANG_HIP(launch_classify(rs, d_hdr + base, out + base, m, kcand, rs->pipe_stream, false));

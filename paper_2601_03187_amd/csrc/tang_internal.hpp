@@ -316,9 +316,11 @@ constexpr size_t kPipeChunk = (size_t)1 << 21;
 // that capture the launches into a graph).
 int classify_async(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id, size_t n,
                    hipStream_t s, tang_stats_t* stats, bool allow_chunks);
+// beside_search: the launch overlaps a search on another stream (the chunked classify),
+// so the predictor leaves room on every SIMD for search waves.
 hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
                       uint32_t* d_cand_packed, float* d_logits, uint8_t* d_cand8,
-                      hipStream_t s);
+                      hipStream_t s, bool beside_search = false);
 int search_host(const tang_ruleset_t* rs, const tang_header_t* hdr, const uint32_t* cand,
                 uint32_t* out, size_t n, uint32_t kcand, uint32_t threads, bool exact,
                 tang_stats_t* stats);
