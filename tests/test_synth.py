@@ -78,3 +78,18 @@ def test_update_stream_and_requests():
     t, sizes, tags = synth.make_requests(1000, 3, seed=13, rate_per_s=1000.0)
     assert (np.diff(t) > 0).all() and sizes.min() >= 32 and sizes.max() <= 65536
     assert set(np.unique(tags).tolist()) == {0, 1, 2}
+
+
+def test_wide_generator_lengths_and_tuples():
+    """wide=True: IP lengths uniform over the 12 WIDE_IP_LENS values per field, so a large
+    ruleset covers all 144 (SIP, DIP) signatures; values stay normalised."""
+    r = synth.make_rules(100_000, seed=9, wide=True)
+    for f in ("sip_len", "dip_len"):
+        vals, counts = np.unique(r[f], return_counts=True)
+        assert vals.tolist() == sorted(synth.WIDE_IP_LENS.tolist())
+        assert np.abs(counts / len(r) - 1 / 12).max() < 0.01
+    sig = r["sip_len"].astype(np.int64) * 64 + r["dip_len"]
+    assert len(np.unique(sig)) == 144
+    L = r["sip_len"].astype(np.uint64)
+    low = np.where(L == 0, np.uint64(0xFFFFFFFF), (np.uint64(1) << (np.uint64(32) - L)) - np.uint64(1))
+    assert ((r["sip"].astype(np.uint64) & low) == 0).all()
