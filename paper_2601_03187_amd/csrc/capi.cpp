@@ -1,5 +1,6 @@
 // C ABI entry points (include/tang.h): argument checks, error codes, and the calls
 // into the host tuple space and the kernels. No C++ exception crosses this boundary.
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -108,19 +109,19 @@ size_t tang_ruleset_s::device_bytes() const {
 
 static void free_device(tang_ruleset_t* rs) {
     if (rs->device == TANG_HOST_ONLY) return;
-    hipSetDevice(rs->device);
+    (void)hipSetDevice(rs->device);
     model_free(rs->model);
-    if (rs->d_slots) dev_release(rs->d_slots);
-    if (rs->d_filter) dev_release(rs->d_filter);
+    if (rs->d_slots) (void)dev_release(rs->d_slots);
+    if (rs->d_filter) (void)dev_release(rs->d_filter);
     rs->d_filter = nullptr;
-    if (rs->d_recs) dev_release(rs->d_recs);
-    if (rs->d_cmask) dev_release(rs->d_cmask);
+    if (rs->d_recs) (void)dev_release(rs->d_recs);
+    if (rs->d_cmask) (void)dev_release(rs->d_cmask);
     rs->d_cmask = nullptr;
-    if (rs->d_tt) dev_release(rs->d_tt);
-    if (rs->d_stats) dev_release(rs->d_stats);
-    for (hipEvent_t e : rs->pipe_events) hipEventDestroy(e);
+    if (rs->d_tt) (void)dev_release(rs->d_tt);
+    if (rs->d_stats) (void)dev_release(rs->d_stats);
+    for (hipEvent_t e : rs->pipe_events) (void)hipEventDestroy(e);
     rs->pipe_events.clear();
-    if (rs->pipe_stream) hipStreamDestroy(rs->pipe_stream);
+    if (rs->pipe_stream) (void)hipStreamDestroy(rs->pipe_stream);
     rs->pipe_stream = nullptr;
     rs->d_slots = nullptr;
     rs->d_recs = nullptr;
@@ -454,8 +455,8 @@ int tang_classify_host(tang_ruleset_t* rs, const tang_header_t* hdr, uint32_t* r
         rc = tang_classify(rs, dh, dout, n, nullptr, stats);
         if (rc == TANG_OK) e = hipMemcpy(rule_id, dout, n * sizeof(uint32_t), hipMemcpyDeviceToHost);
     }
-    dev_release(dh);
-    if (dout) dev_release(dout);
+    (void)dev_release(dh);
+    if (dout) (void)dev_release(dout);
     if (e != hipSuccess) return hip_fail(e, "tang_classify_host");
     return rc;
     TANG_GUARD_END

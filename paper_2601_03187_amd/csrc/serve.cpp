@@ -249,12 +249,12 @@ static void free_server(tang_server_t* srv) {
         if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
     for (auto& s : srv->slots) {
         if (s.stream) hipStreamSynchronize(s.stream);
-        if (s.ev) hipEventDestroy(s.ev);
-        if (s.stream) hipStreamDestroy(s.stream);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
         if (s.h_hdr) hipHostFree(s.h_hdr);
         if (s.h_out) hipHostFree(s.h_out);
-        if (s.d_hdr) dev_release(s.d_hdr);
-        if (s.d_out) dev_release(s.d_out);
+        if (s.d_hdr) (void)dev_release(s.d_hdr);
+        if (s.d_out) (void)dev_release(s.d_out);
     }
     delete srv;
 }

@@ -316,7 +316,7 @@ int upload_all(tang_ruleset_t* rs) {
             e = launch_conflict_build(d_boxes, boxes.size(), rs->d_recs, rs->d_cmask, rs->nw,
                                       rs->d_tt->all_mask, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        dev_release(d_boxes);
+        (void)dev_release(d_boxes);
         if (e != hipSuccess) return hip_fail(e, "conflict-mask build");
     }
     return TANG_OK;
@@ -465,13 +465,13 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
                                    hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e == hipSuccess) {
-                dev_release(rs->d_slots);
-                dev_release(rs->d_filter);
+                (void)dev_release(rs->d_slots);
+                (void)dev_release(rs->d_filter);
                 rs->d_slots = ns;
                 rs->d_filter = nf;
             } else {
-                if (ns) dev_release(ns);
-                if (nf) dev_release(nf);
+                if (ns) (void)dev_release(ns);
+                if (nf) (void)dev_release(nf);
             }
         } else if (!touched_slots.empty()) {
             std::sort(touched_slots.begin(), touched_slots.end());
