@@ -162,7 +162,7 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 
 // NW: conflict-mask words (1 for at most 32 tuples, kMaskWords for up to 256). Tuple
 // sets are NW-word bit masks (word t / 32, bit t % 32); everything else is as for one word.
-template <bool STATS, int NW>
+template <bool STATS, int NW, bool RANKED>
 __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                                                   uint32_t* __restrict__ out, uint32_t n,
                                                   const Slot* __restrict__ slots,
@@ -174,6 +174,7 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
     constexpr uint32_t NT = 32u * NW;
     __shared__ TupleDev s_t[NT];
     __shared__ uint2 s_rank[NT];  // best keys in ascending order
+    __shared__ uint32_t s_order[NT];  // tuple indices in that order
     __shared__ uint32_t s_prefix[NT + 1][NW];
     __shared__ uint32_t s_all[NW];
     __shared__ uint32_t s_misc[4];
@@ -186,6 +187,7 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
     for (uint32_t k = tid; k < NT; k += 256u) {
         s_t[k] = ttg->t[k];
         s_rank[k] = make_uint2(ttg->rank_prio[k], ttg->rank_id[k]);
+        s_order[k] = ttg->order[k];
     }
     for (uint32_t k = tid; k < (NT + 1) * NW; k += 256u) s_prefix[k / NW][k % NW] = ttg->prefix[k / NW][k % NW];
     if (tid < NW) s_all[tid] = ttg->all_mask[tid];
@@ -321,6 +323,59 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
             }
         }
     }
+    uint32_t steps = 0;
+    if constexpr (RANKED) {
+        // Without candidates (no model), one mask word: the tuples go in rank order
+        // (ascending best key), eight ranks per batch -- the filter bits of the batch's
+        // tuples this lane still needs, eight loads issued back to back, then this lane's
+        // probes of the passing ones. A tuple is needed while its best key beats the
+        // answer, so an answer found in an early batch drops the lane's later tuples
+        // before their filter loads (8.1 instead of 12.3 per header at 512k rules): the
+        // vector-memory data path is busy nearly all of the kernel's time. Batches no
+        // lane needs are skipped. (With candidates most lanes enter certification with
+        // an answer already, and this variant's 40 VGPRs cost more beside the predictor
+        // than its loads save.)
+        static_assert(NW == 1, "rank batches use one mask word");
+        for (uint32_t r0 = 0; r0 < ntup; r0 += 8) {
+            uint32_t want = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t r = r0 + q;
+                if (r < ntup && ((todo[0] >> s_order[r]) & 1u) &&
+                    kless(s_rank[r].x, s_rank[r].y, b.prio, b.id))
+                    want |= 1u << q;
+            }
+            if (!wave_or(want)) continue;
+            if (STATS) ++n_rounds;
+            uint32_t wd[8], pos[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                wd[q] = 0;
+                pos[q] = 0;
+                if ((want >> q) & 1u) {
+                    const uint32_t t = s_order[r0 + q];
+                    const uint32_t bit =
+                        filter_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask) & filter_mask;
+                    wd[q] = filter[bit >> 5];
+                    pos[q] = bit & 31u;
+                    if (STATS) ++n_filter;
+                }
+            }
+            uint32_t pass = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) pass |= ((wd[q] >> pos[q]) & 1u) << q;
+            while (pass) {
+                const int q = __builtin_ctz(pass);
+                pass &= pass - 1u;
+                if (STATS) ++steps;
+                const uint32_t t = s_order[r0 + q];
+                if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) continue;
+                const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
+                search_tuple<STATS>(t, key_hash(t, ms, md), ms, md, sip, dip, sp, dp, proto,
+                                    slot_mask, slots, recs, b, n_probe, n_slots, n_recs);
+            }
+        }
+    } else {
     // Phase 1: the filter bits of every remaining tuple, eight tuples per batch with their
     // loads issued back to back; `hits` keeps the tuples whose bit is set. With one mask
     // word a batch is eight consecutive tuples (batches no lane of the wave needs are
@@ -400,7 +455,6 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
     // Phase 2: each lane searches its own passing tuples (so a wave takes as many steps as
     // its busiest lane, not as the union of its lanes' tuples), skipping any whose best key
     // can no longer beat the answer; the order does not matter for the result.
-    uint32_t steps = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         while (hits[w]) {
@@ -412,6 +466,7 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
             search_tuple<STATS>(t, key_hash(t, ms, md), ms, md, sip, dip, sp, dp, proto, slot_mask,
                                 slots, recs, b, n_probe, n_slots, n_recs);
         }
+    }
     }
     if (STATS) n_steps = wave_max(steps);
     if (active) {
@@ -456,12 +511,15 @@ hipError_t launch_classify(const tang_ruleset_t* rs, const tang_header_t* d_hdr,
             hipLaunchKernelGGL(kern, grid, block, 0, s, h, d_out + base, m, rs->d_slots, rs->d_recs,
                                rs->d_cmask, rs->d_filter, rs->d_tt, kcand, rs->d_stats);
         };
-        if (rs->nw == 1) {
-            if (stats) go(k_classify<true, 1>);
-            else go(k_classify<false, 1>);
+        if (rs->nw == 1 && kcand == 0) {
+            if (stats) go(k_classify<true, 1, true>);
+            else go(k_classify<false, 1, true>);
+        } else if (rs->nw == 1) {
+            if (stats) go(k_classify<true, 1, false>);
+            else go(k_classify<false, 1, false>);
         } else {
-            if (stats) go(k_classify<true, kMaskWords>);
-            else go(k_classify<false, kMaskWords>);
+            if (stats) go(k_classify<true, kMaskWords, false>);
+            else go(k_classify<false, kMaskWords, false>);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
