@@ -4,7 +4,7 @@
  * The method is TaNG's two-stage classification (Sec. 5.1.1): a small MLP reads each
  * packet header and predicts which tuple of a tuple space (Sec. 4.3) holds the answer;
  * the packet's SIP/DIP are truncated to that tuple's prefix lengths, hashed, and the
- * hashed bucket's rules are compared one by one. Unlike the paper, which accepts a
+ * hashed bucket's rules are checked in (priority, id) order. Unlike the paper, which accepts a
  * rare lower-priority answer (Sec. 5.1.1, Sec. 8), this library certifies every
  * answer: after the predicted tuples it probes each tuple that holds a higher-priority
  * rule overlapping the match found (a per-rule "conflict mask"), or every remaining
