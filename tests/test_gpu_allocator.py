@@ -65,3 +65,49 @@ def test_internal_memory_through_callers_allocator():
         assert calls["free"] == calls["alloc"]
     finally:
         T.tang_set_allocator()
+
+
+def test_serving_loop_slots_through_callers_allocator():
+    """The serving loop's device slots come from the caller's allocator too and go back
+    on destroy; its answers are the oracle's."""
+    torch_cuda()
+    live = {}
+    talloc, tfree = T.torch_allocator()
+
+    def alloc(nbytes, dev):
+        p = talloc(nbytes, dev)
+        if p:
+            live[p] = nbytes
+        return p
+
+    def free(p, dev):
+        assert live.pop(p, None) is not None, hex(p)
+        tfree(p, dev)
+
+    T.tang_set_allocator(alloc, free)
+    try:
+        rules = synth.make_rules(3000, seed=85)
+        rs = T.tang_ruleset_create(0, rules)
+        srv = None
+        try:
+            T.tang_model_load(rs, *train.random_weights(T.tang_ruleset_num_tuples(rs), 128, seed=4), "bf16")
+            n_before = len(live)
+            srv = T.tang_server_create(0, n_streams=2, max_batch=4096, use_graphs=1)
+            tag = T.tang_server_add_ruleset(srv, rs)
+            assert len(live) > n_before  # the slots
+            reqs = []
+            for q in range(12):
+                hdr = synth.make_packets(rules, 100 + 300 * q, seed=86 + q, frac_in=0.8)
+                out = np.full(len(hdr), 0xDEADBEEF, dtype=np.uint32)
+                reqs.append((hdr, out, T.tang_server_submit(srv, tag, hdr, out)))
+            for hdr, out, r in reqs:
+                T.tang_server_wait(r, 60_000_000)
+                assert np.array_equal(out, orc.classify(rules, hdr))
+                T.tang_server_req_free(r)
+        finally:
+            if srv is not None:
+                T.tang_server_destroy(srv)
+            T.tang_ruleset_destroy(rs)
+        assert not live, f"{len(live)} blocks not returned"
+    finally:
+        T.tang_set_allocator()
