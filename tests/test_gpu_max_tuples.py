@@ -1,0 +1,121 @@
+"""The largest tuple space a ruleset holds: 256 tuples, every pair of 16 prefix lengths
+(Sec. 4.3's (SIP length, DIP length) signatures). All eight conflict-mask words are in use,
+tuple 255 is a valid candidate in the packed top-k word, the output layer has 256 classes
+(eight 32-class blocks under the running top-k), restricted insertion (Sec. 5.2.1) keeps
+the count at 256, and an insert that would need a 257th tuple fails without changing the
+answers. Every answer equals the oracle's linear scan."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2601_03187_amd import synth, train
+from paper_2601_03187_amd import tang as T
+from tests._gpu import classify_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+LENS16 = np.array([32, 30, 28, 26, 24, 22, 20, 18, 16, 14, 12, 10, 8, 6, 4, 2])
+
+
+def grid_rules(n: int, seed: int) -> np.ndarray:
+    """n rules (a multiple of 256) spread evenly over the 16 x 16 length pairs, in a
+    shuffled order; the other fields as the wide generator draws them."""
+    assert n % 256 == 0
+    r = synth.make_rules(n, seed=seed, wide=True)
+    rng = np.random.default_rng(seed + 1)
+    pair = rng.permutation(np.arange(n) % 256)
+    r["sip_len"] = LENS16[pair % 16]
+    r["dip_len"] = LENS16[pair // 16]
+    r["sip"] &= synth._keep_bits(r["sip_len"]).astype(np.uint32)
+    r["dip"] &= synth._keep_bits(r["dip_len"]).astype(np.uint32)
+    return r
+
+
+def test_max_tuples_conflict_masks_equal_bruteforce():
+    """1,024 rules, priorities with ties: every rule's 256-bit mask equals the brute-force
+    mask, and some masks reach into the last word (tuples 224..255)."""
+    torch_cuda()
+    rules = grid_rules(1024, seed=81)
+    rules["priority"] = np.random.default_rng(1).integers(0, 64, len(rules))
+    rt = orc.rule_tuples(rules)
+    want = orc.conflict_masks(rules, rt)
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        assert T.tang_ruleset_num_tuples(rs) == T.TANG_MAX_TUPLES
+        assert max(int(w) for w in want) >> 224
+        for k in range(len(rules)):
+            assert T.tang_ruleset_rule_tuple(rs, int(rules[k]["id"])) == rt[k]
+            assert T.tang_ruleset_conflict_mask(rs, int(rules[k]["id"])) == int(want[k]), k
+    finally:
+        T.tang_ruleset_destroy(rs)
+
+
+def test_max_tuples_classify_every_predictor_and_updates():
+    """32,768 rules over 256 tuples, 100,003 headers (70% inside rules; some of the rest
+    match nothing, since no tuple has a zero-length prefix)."""
+    torch_cuda()
+    rules = grid_rules(32768, seed=82)
+    hdr = synth.make_packets(rules, 100_003, seed=83, frac_in=0.7)
+    want = orc.classify(rules, hdr)
+    assert (want == orc.NO_MATCH).mean() > 0.01
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        C = T.tang_ruleset_num_tuples(rs)
+        assert C == 256
+        assert np.array_equal(classify_dev(rs, hdr), want)
+        Ws, bs, sc, acc = train.fit(rs, rules, hdr[:50_000], 256, steps=300, seed=7,
+                                    rule_ids=want[:50_000], device="cuda")
+        Wr, br = train.random_weights(C, 256, seed=8)
+        X = train.feature_bits_torch(hdr[:65536], device="cuda")
+        scr = train.act_scales(Wr, br, X)
+        for name, (W, b, s) in {"trained": (Ws, bs, sc), "random": (Wr, br, scr)}.items():
+            for prec in ("fp32", "bf16", "fp8"):
+                for k in (1, 4):
+                    T.tang_model_load(rs, W, b, prec, topk=k, act_scales=s if prec == "fp8" else None)
+                    assert np.array_equal(classify_dev(rs, hdr), want), (name, prec, k)
+        # a constant winner at the last tuple: its index (255) rides in every candidate word
+        Wc, bc = train.constant_winner_weights(C, 128, C - 1)
+        T.tang_model_load(rs, Wc, bc, "bf16", topk=2)
+        assert np.array_equal(classify_dev(rs, hdr), want)
+        rng = np.random.default_rng(9)
+        Wn = [rng.normal(0, 2.0, (512, 7))] + [rng.normal(0, 1 / np.sqrt(512), (512, 512)) for _ in range(4)]
+        Wn.append(rng.normal(0, 1 / np.sqrt(512), (C, 512)))
+        bn = [rng.normal(0, 0.05, w.shape[0]) for w in Wn]
+        T.tang_model_load_resnet(rs, [w.astype(np.float32) for w in Wn],
+                                 [b.astype(np.float32) for b in bn], "bf16", topk=2)
+        assert np.array_equal(classify_dev(rs, hdr), want)
+
+        # updates: lengths between the grid's go to coarser tuples; the count stays 256
+        T.tang_model_load(rs, Ws, bs, "bf16", topk=2)
+        all_rules = rules.copy()
+        live = set(int(i) for i in rules["id"])
+        ups = synth.make_update_stream(rules, rounds=2, per_round=300, seed=84,
+                                       prio_range=len(rules))
+        for rd, (ins, dels) in enumerate(ups):
+            ins["sip_len"] = rng.choice(np.arange(2, 33), len(ins))
+            ins["dip_len"] = rng.choice(np.arange(2, 33), len(ins))
+            ins["sip"] &= synth._keep_bits(ins["sip_len"]).astype(np.uint32)
+            ins["dip"] &= synth._keep_bits(ins["dip_len"]).astype(np.uint32)
+            T.tang_insert(rs, ins)
+            T.tang_delete(rs, dels)
+            all_rules = np.concatenate([all_rules, ins])
+            live |= set(int(i) for i in ins["id"])
+            live -= set(int(i) for i in dels)
+            lm = np.isin(all_rules["id"], np.fromiter(live, dtype=np.uint32))
+            assert T.tang_ruleset_num_tuples(rs) == 256
+            pk = synth.make_packets(all_rules[lm], 60_000, seed=300 + rd, frac_in=0.8)
+            assert np.array_equal(classify_dev(rs, pk), orc.classify(all_rules, pk, live=lm)), rd
+        # a signature below every tuple would be a 257th: refused, nothing changes
+        extra = all_rules[:1].copy()
+        extra["id"] = np.uint32(10_000_000)
+        extra["sip_len"] = 0
+        extra["sip"] = 0
+        n_live = T.tang_ruleset_num_rules(rs)
+        with pytest.raises(T.TangError) as e:
+            T.tang_insert(rs, extra)
+        assert e.value.name == "EINVAL"
+        assert T.tang_ruleset_num_tuples(rs) == 256 and T.tang_ruleset_num_rules(rs) == n_live
+        pk = synth.make_packets(all_rules[lm], 60_000, seed=400, frac_in=0.8)
+        assert np.array_equal(classify_dev(rs, pk), orc.classify(all_rules, pk, live=lm))
+    finally:
+        T.tang_ruleset_destroy(rs)
