@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
     const uint32_t i = blockIdx.x * 256u + tid;
     uint32_t n_probe = 0, n_slots = 0, n_recs = 0, top1 = 0, fb = 0, nm = 0, active = 0;
     uint32_t n_filter = 0, n_steps = 0, n_rounds = 0;
-    uint32_t sip = 0, dip = 0, sp = 0, dp = 0, proto = 0, c0 = 0xFFu;
+    uint32_t sip = 0, dip = 0, sp = 0, dp = 0, proto = 0, c0 = kNoTuple;
     uint32_t todo[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) todo[w] = 0;

@@ -62,7 +62,9 @@ def test_max_tuples_classify_every_predictor_and_updates():
     try:
         C = T.tang_ruleset_num_tuples(rs)
         assert C == 256
-        assert np.array_equal(classify_dev(rs, hdr), want)
+        got, st = classify_dev(rs, hdr, stats=True)
+        assert np.array_equal(got, want)
+        assert st["top1_hits"] == 0   # no model: no first candidate, even for tuple 255
         Ws, bs, sc, acc = train.fit(rs, rules, hdr[:50_000], 256, steps=300, seed=7,
                                     rule_ids=want[:50_000], device="cuda")
         Wr, br = train.random_weights(C, 256, seed=8)
@@ -76,7 +78,9 @@ def test_max_tuples_classify_every_predictor_and_updates():
         # a constant winner at the last tuple: its index (255) rides in every candidate word
         Wc, bc = train.constant_winner_weights(C, 128, C - 1)
         T.tang_model_load(rs, Wc, bc, "bf16", topk=2)
-        assert np.array_equal(classify_dev(rs, hdr), want)
+        got, st = classify_dev(rs, hdr, stats=True)
+        assert np.array_equal(got, want)
+        assert st["top1_hits"] == int((orc.rule_tuples(rules)[want[want != orc.NO_MATCH]] == C - 1).sum())
         rng = np.random.default_rng(9)
         Wn = [rng.normal(0, 2.0, (512, 7))] + [rng.normal(0, 1 / np.sqrt(512), (512, 512)) for _ in range(4)]
         Wn.append(rng.normal(0, 1 / np.sqrt(512), (C, 512)))
