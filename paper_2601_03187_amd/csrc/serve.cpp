@@ -77,17 +77,21 @@ struct tang_server_s {
 
     void loop();
     void finish(StreamSlot& s, int status);
-    int launch(uint32_t slot_idx, uint32_t tag, std::vector<std::shared_ptr<ReqState>>& batch,
-               size_t total);
-    int graph_for(uint32_t tag, uint32_t cls, uint32_t slot_idx, hipGraphExec_t* out);
+    int launch(uint32_t slot_idx, uint32_t tag, tang_ruleset_t* rs, bool warm,
+               std::vector<std::shared_ptr<ReqState>>& batch, size_t total);
+    int graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uint32_t slot_idx,
+                  hipGraphExec_t* out);
 };
 
 using namespace tang;
 
 static constexpr size_t kPktBytes = sizeof(tang_header_t) + sizeof(uint32_t);
 
-int tang_server_s::graph_for(uint32_t tag, uint32_t cls, uint32_t si, hipGraphExec_t* out) {
-    tang_ruleset_t* rs = rulesets[tag];
+// Only the loop thread calls launch and graph_for; `rulesets` and `warmed` may grow under
+// `mu` meanwhile (tang_server_add_ruleset), so the loop reads them under `mu` and passes
+// the ruleset and its warm-up flag in.
+int tang_server_s::graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uint32_t si,
+                             hipGraphExec_t* out) {
     GraphEntry& g = graphs[std::make_tuple(tag, cls, si)];
     if (g.exec && g.version == rs->version) {
         *out = g.exec;
@@ -118,10 +122,9 @@ int tang_server_s::graph_for(uint32_t tag, uint32_t cls, uint32_t si, hipGraphEx
     return TANG_OK;
 }
 
-int tang_server_s::launch(uint32_t si, uint32_t tag, std::vector<std::shared_ptr<ReqState>>& batch,
-                          size_t total) {
+int tang_server_s::launch(uint32_t si, uint32_t tag, tang_ruleset_t* rs, bool warm,
+                          std::vector<std::shared_ptr<ReqState>>& batch, size_t total) {
     StreamSlot& s = slots[si];
-    tang_ruleset_t* rs = rulesets[tag];
     s.reqs = batch;
     s.offs.clear();
     s.total = total;
@@ -135,17 +138,16 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, std::vector<std::shared_ptr
     while (cls < total) cls <<= 1;
     TANG_HIP(hipMemcpyAsync(s.d_hdr, s.h_hdr, total * sizeof(tang_header_t), hipMemcpyHostToDevice,
                             s.stream));
-    if (!warmed[tag]) {  // first use: eager call sets up kernel attributes before any capture
+    if (!warm) {  // first use: eager call sets up kernel attributes before any capture
         int rc = classify_async(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr, false);
         if (rc) return rc;
         TANG_HIP(hipStreamSynchronize(s.stream));
-        warmed[tag] = 1;
     }
     // the residual predictor orders its shared workspace with an event across calls, which
     // a captured graph cannot hold: its batches run eagerly
     if (cfg.use_graphs && rs->model.kind == 0) {
         hipGraphExec_t exec = nullptr;
-        int rc = graph_for(tag, (uint32_t)cls, si, &exec);
+        int rc = graph_for(tag, rs, (uint32_t)cls, si, &exec);
         if (rc) return rc;
         TANG_HIP(hipGraphLaunch(exec, s.stream));
     } else {
@@ -222,8 +224,10 @@ void tang_server_s::loop() {
             inflight_bytes += total * kPktBytes;
             const uint64_t t = now_ns();
             for (auto& r : batch) r->t_admit = t;
+            tang_ruleset_t* rs = rulesets[tag];
+            const bool warm = warmed[tag] != 0;
             lk.unlock();
-            int rc = launch(si, tag, batch, total);
+            int rc = launch(si, tag, rs, warm, batch, total);
             if (rc != TANG_OK) {
                 StreamSlot& s = slots[si];
                 s.reqs = batch;
@@ -233,6 +237,7 @@ void tang_server_s::loop() {
             }
             progressed = true;
             lk.lock();
+            if (rc == TANG_OK) warmed[tag] = 1;
         }
         if (!progressed) {
             any_busy = false;

@@ -80,3 +80,38 @@ def test_alone_equals_mix(graphs, limit):
         T.tang_server_destroy(srv)
         for _, rs in sets:
             T.tang_ruleset_destroy(rs)
+
+
+def test_rulesets_added_while_serving():
+    """Rulesets added while batches of earlier ones are in flight (the server's ruleset
+    table grows from 1 to 17 entries meanwhile): every request's answers equal the
+    oracle's."""
+    torch_cuda()
+    sets = []
+    for k in range(17):
+        rules = synth.make_rules(400 + 50 * k, seed=700 + k)
+        rs = T.tang_ruleset_create(0, rules)
+        if k % 2:
+            C = T.tang_ruleset_num_tuples(rs)
+            Ws, bs = train.random_weights(C, 128, seed=k)
+            T.tang_model_load(rs, Ws, bs, "bf16")
+        sets.append((rules, rs))
+    srv = T.tang_server_create(0, n_streams=2, max_batch=4096, use_graphs=1)
+    try:
+        tags, reqs = [], []
+        for k, (rules, rs) in enumerate(sets):
+            tags.append(T.tang_server_add_ruleset(srv, rs))
+            for q in range(4):
+                tag = tags[(k + q) % len(tags)]
+                hdr = synth.make_packets(sets[tag][0], 1000 + 700 * q, seed=2000 + 10 * k + q, frac_in=0.8)
+                out = np.full(len(hdr), 0xDEADBEEF, dtype=np.uint32)
+                reqs.append((tag, hdr, out, T.tang_server_submit(srv, tag, hdr, out)))
+        assert tags == list(range(17))
+        for tag, hdr, out, r in reqs:
+            T.tang_server_wait(r, 60_000_000)
+            assert np.array_equal(out, orc.classify(sets[tag][0], hdr)), tag
+            T.tang_server_req_free(r)
+    finally:
+        T.tang_server_destroy(srv)
+        for _, rs in sets:
+            T.tang_ruleset_destroy(rs)
