@@ -303,7 +303,12 @@ typedef struct tang_server_s tang_server_t;
 typedef struct tang_req_s tang_req_t;
 
 int tang_server_create(int device, const tang_server_cfg_t* cfg, tang_server_t** out);
-/* Register a ruleset (same device); *tag identifies it in submits. */
+/*
+ * Register a ruleset (same device); *tag identifies it in submits. May be called while
+ * the server runs. The ruleset stays the caller's: an update or model load on it must
+ * not overlap its outstanding requests (wait for them first); later batches capture
+ * their graphs again.
+ */
 int tang_server_add_ruleset(tang_server_t* srv, tang_ruleset_t* rs, uint32_t* tag);
 /*
  * Submit n host headers for ruleset `tag`; results go to host array out[n] when the
@@ -319,6 +324,7 @@ int tang_server_poll(const tang_req_t* req);
 /* Timestamps in ns on the host steady clock: submitted, admitted, completed. */
 int tang_server_req_times(const tang_req_t* req, uint64_t* submit_ns, uint64_t* admit_ns,
                           uint64_t* done_ns);
+/* Frees the handle; a request still running completes (hdr and out must stay valid). */
 void tang_server_req_free(tang_req_t* req);
 /* Drains pending work, stops the loop, frees the server (not the rulesets). */
 int tang_server_destroy(tang_server_t* srv);
