@@ -52,6 +52,31 @@ def measured_traffic(kernel: str, workload: str):
     return t.get("traffic_bytes_per_launch")
 
 
+def library_gather(dev, table_bytes: int) -> dict:
+    """For scale: independent random 4-byte gathers through torch's indexing kernel over a
+    table as large as the ruleset's device memory (so it sits where the search's tables
+    sit: the Infinity Cache, not HBM), 2^26 indices, mean of 5 launches."""
+    import torch
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    words = table_bytes // 4
+    tab = torch.randint(0, 1 << 30, (words,), dtype=torch.int32, device=dev, generator=g)
+    n_idx = 1 << 26
+    idx = torch.randint(0, words, (n_idx,), device=dev, generator=g)
+    res = tab[idx]
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(5):
+        res = tab[idx]
+    b.record()
+    torch.cuda.synchronize()
+    rate = n_idx / (a.elapsed_time(b) / 5 * 1e-3)
+    del tab, idx, res
+    return {"table_bytes": int(words * 4), "indices": n_idx, "gathers_per_s": rate,
+            "how": "torch advanced indexing, 4-byte elements"}
+
+
 def pct(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
@@ -318,6 +343,22 @@ def main():
              "k_classify": {"bound": "hbm", "achieved_gbs": head["search_gbs"],
                             "frac": head["search_gbs"] / PEAK_HBM_GBS, "ms": head["k_classify_ms"],
                             "bytes_per_pkt": head["search_bytes_per_pkt"]}}
+    # the search's random accesses (filter words, slots, records: one line each) per second,
+    # beside a plain library gather over a table of the same size
+    acc_pkt = head["filter_checks_per_pkt"] + head["slots_per_pkt"] + head["records_per_pkt"]
+    rnd = {"search_random_accesses_per_pkt": acc_pkt,
+           "search_random_accesses_per_s": acc_pkt * n / (head["k_classify_ms"] * 1e-3)}
+    try:
+        rnd["library_gather"] = library_gather(dev, T.tang_ruleset_device_bytes(rs))
+        rnd["search_vs_library_gather"] = (rnd["search_random_accesses_per_s"]
+                                           / rnd["library_gather"]["gathers_per_s"])
+        log(f"[bench] search {rnd['search_random_accesses_per_s'] / 1e9:.1f} G random accesses/s "
+            f"({acc_pkt:.2f} per header); torch gather over {rnd['library_gather']['table_bytes']} B: "
+            f"{rnd['library_gather']['gathers_per_s'] / 1e9:.1f} G/s")
+    except Exception as ex:  # a reference figure only: never costs the bench line
+        rnd["library_gather"] = None
+        log(f"[bench] library gather reference failed: {ex}")
+    other["k_classify"]["random_access"] = rnd
     line = {
         "metric": "Mpps classified at 512k rules (1 MI355X)",
         "value": head["mpps"], "unit": "Mpps", "n_gpus": 1, "steps": args.steps,
