@@ -54,8 +54,8 @@ def measured_traffic(kernel: str, workload: str):
 
 def library_gather(dev, table_bytes: int) -> dict:
     """For scale: independent random 4-byte gathers through torch's indexing kernel over a
-    table as large as the ruleset's device memory (so it sits where the search's tables
-    sit: the Infinity Cache, not HBM), 2^26 indices, mean of 5 launches."""
+    table as large as the search's tables (so it sits where they sit: the Infinity Cache,
+    not HBM), 2^26 indices, mean of 5 launches."""
     import torch
     g = torch.Generator(device=dev)
     g.manual_seed(5)
@@ -153,7 +153,8 @@ def main():
     rs = T.tang_ruleset_create(0, rules)
     build_s = time.time() - t0
     C = T.tang_ruleset_num_tuples(rs)
-    log(f"[bench] ruleset built in {build_s:.2f}s, {C} tuples, {T.tang_ruleset_device_bytes(rs)} device bytes")
+    table_bytes = T.tang_ruleset_device_bytes(rs)  # before any model: the search's tables
+    log(f"[bench] ruleset built in {build_s:.2f}s, {C} tuples, {table_bytes} device bytes")
     d_hdr = torch.from_numpy(hdr.view(np.uint8).reshape(-1)).to(dev)
     d_out = torch.empty(n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
@@ -349,7 +350,7 @@ def main():
     rnd = {"search_random_accesses_per_pkt": acc_pkt,
            "search_random_accesses_per_s": acc_pkt * n / (head["k_classify_ms"] * 1e-3)}
     try:
-        rnd["library_gather"] = library_gather(dev, T.tang_ruleset_device_bytes(rs))
+        rnd["library_gather"] = library_gather(dev, table_bytes)
         rnd["search_vs_library_gather"] = (rnd["search_random_accesses_per_s"]
                                            / rnd["library_gather"]["gathers_per_s"])
         log(f"[bench] search {rnd['search_random_accesses_per_s'] / 1e9:.1f} G random accesses/s "
