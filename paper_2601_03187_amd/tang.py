@@ -1,7 +1,9 @@
 """ctypes binding of libtang.so (include/tang.h). Argument marshalling only.
 
 Every function keeps the C name. Device buffers may be passed as integers (device
-addresses) or as objects with ``data_ptr()`` (torch tensors); streams as integers or
+addresses, unchecked) or as torch tensors (checked: on a GPU, contiguous, and large
+enough for the call's n, so a wrong n raises instead of reaching past a buffer's end);
+streams as integers or
 objects with a ``cuda_stream`` attribute (torch streams). A non-zero return code raises
 ``TangError`` carrying the library's message. Nothing here computes any part of the
 classification: if the library is missing, importing this module fails.
@@ -125,16 +127,26 @@ def _check(rc: int):
         raise TangError(rc, _lib.tang_last_error().decode())
 
 
-def _ptr(x):
-    if x is None:
-        return None
-    if isinstance(x, int):
+def _dbuf(x, nbytes: int, what: str):
+    """Device pointer for a call that reads or writes nbytes through it. A torch tensor is
+    checked (on a GPU, contiguous, large enough) so that a wrong n cannot send a kernel
+    past the buffer's end; an int is taken as the caller's own device pointer; None goes
+    through (the library rejects it when n > 0)."""
+    if x is None or isinstance(x, int):
         return x
     if hasattr(x, "data_ptr"):
+        if not x.is_cuda:
+            raise ValueError(f"{what}: a device tensor is needed")
+        if not x.is_contiguous():
+            raise ValueError(f"{what}: the tensor must be contiguous")
+        have = x.numel() * x.element_size()
+        if have < nbytes:
+            raise ValueError(f"{what}: {have} bytes, the call needs {nbytes}")
         return x.data_ptr()
-    if isinstance(x, np.ndarray):
-        return x.ctypes.data
-    raise TypeError(f"cannot take a pointer of {type(x)}")
+    raise TypeError(f"{what}: a device tensor or an int device pointer is needed, not {type(x)}")
+
+
+_model_topk = {}  # ruleset handle -> candidates per header of its loaded model
 
 
 def _stream(s):
@@ -163,6 +175,7 @@ def tang_ruleset_create(device: int, rules) -> int:
 
 def tang_ruleset_destroy(rs: int) -> None:
     _lib.tang_ruleset_destroy(rs)
+    _model_topk.pop(rs, None)
 
 
 def tang_ruleset_num_tuples(rs: int) -> int:
@@ -222,6 +235,7 @@ def tang_model_load(rs: int, Ws, bs, precision="fp32", topk: int = 1, act_scales
         sc = np.ascontiguousarray(np.asarray(act_scales, dtype=np.float32))
     _check(_lib.tang_model_load(rs, ctypes.byref(d), ctypes.cast(wp, _P), ctypes.cast(bp, _P), p,
                                 sc.ctypes.data if sc is not None else None))
+    _model_topk[rs] = int(topk)
 
 
 def tang_search_host(rs: int, hdr: np.ndarray, cand=None, kcand: int = 0, threads: int = 1,
@@ -269,28 +283,33 @@ def tang_model_load_resnet(rs: int, Ws, bs, precision="bf16", topk: int = 1) -> 
     wp = (ctypes.c_void_p * len(Ws))(*[w.ctypes.data for w in Ws])
     bp = (ctypes.c_void_p * len(bs))(*[b.ctypes.data for b in bs])
     _check(_lib.tang_model_load_resnet(rs, ctypes.byref(d), ctypes.cast(wp, _P), ctypes.cast(bp, _P), p))
+    _model_topk[rs] = int(topk)
 
 
 def tang_model_unload(rs: int) -> None:
     _check(_lib.tang_model_unload(rs))
+    _model_topk.pop(rs, None)
 
 
 # --- classify ---------------------------------------------------------------------------
 
 def tang_classify(rs: int, d_hdr, d_rule_id, n: int, stream=None, want_stats: bool = False):
     st = tang_stats_t() if want_stats else None
-    _check(_lib.tang_classify(rs, _ptr(d_hdr), _ptr(d_rule_id), n, _stream(stream),
+    _check(_lib.tang_classify(rs, _dbuf(d_hdr, 16 * n, "d_hdr"), _dbuf(d_rule_id, 4 * n, "d_rule_id"),
+                              n, _stream(stream),
                               ctypes.byref(st) if st is not None else None))
     return st.as_dict() if st is not None else None
 
 
 def tang_predict(rs: int, d_hdr, d_io, n: int, stream=None) -> None:
-    _check(_lib.tang_predict(rs, _ptr(d_hdr), _ptr(d_io), n, _stream(stream)))
+    _check(_lib.tang_predict(rs, _dbuf(d_hdr, 16 * n, "d_hdr"), _dbuf(d_io, 4 * n, "d_io"), n,
+                             _stream(stream)))
 
 
 def tang_search(rs: int, d_hdr, d_io, n: int, stream=None, want_stats: bool = False):
     st = tang_stats_t() if want_stats else None
-    _check(_lib.tang_search(rs, _ptr(d_hdr), _ptr(d_io), n, _stream(stream),
+    _check(_lib.tang_search(rs, _dbuf(d_hdr, 16 * n, "d_hdr"), _dbuf(d_io, 4 * n, "d_io"), n,
+                            _stream(stream),
                             ctypes.byref(st) if st is not None else None))
     return st.as_dict() if st is not None else None
 
@@ -308,7 +327,11 @@ def tang_classify_host(rs: int, hdr: np.ndarray, want_stats: bool = False):
 
 
 def tang_mlp_forward(rs: int, d_hdr, n: int, d_logits=None, d_cand=None, stream=None) -> None:
-    _check(_lib.tang_mlp_forward(rs, _ptr(d_hdr), n, _ptr(d_logits), _ptr(d_cand), _stream(stream)))
+    C = tang_ruleset_num_tuples(rs)
+    k = _model_topk.get(rs, 1)
+    _check(_lib.tang_mlp_forward(rs, _dbuf(d_hdr, 16 * n, "d_hdr"), n,
+                                 _dbuf(d_logits, 4 * n * C, "d_logits"),
+                                 _dbuf(d_cand, n * k, "d_cand"), _stream(stream)))
 
 
 # --- updates ----------------------------------------------------------------------------

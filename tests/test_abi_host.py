@@ -255,3 +255,15 @@ def test_allocator_callbacks_come_in_pairs():
         T.tang_set_allocator(lambda n, d: 0, None)
     assert e.value.name == "EINVAL"
     T.tang_set_allocator()
+
+
+def test_binding_checks_device_buffers():
+    """The binding hands a torch tensor to the library only if it is on a GPU, contiguous
+    and large enough for the call; ints pass as the caller's own device pointers."""
+    import torch
+    with pytest.raises(ValueError, match="device tensor"):
+        T._dbuf(torch.zeros(4, dtype=torch.int32), 16, "d_rule_id")
+    with pytest.raises(TypeError):
+        T._dbuf(np.zeros(4, dtype=np.uint32), 16, "d_rule_id")  # host memory
+    assert T._dbuf(None, 16, "d_hdr") is None
+    assert T._dbuf(0x1000, 1 << 40, "d_hdr") == 0x1000

@@ -248,6 +248,33 @@ def test_empty_and_ragged_batches():
         T.tang_ruleset_destroy(rs)
 
 
+def test_binding_refuses_buffers_shorter_than_n():
+    """A wrong n from Python raises before any kernel runs; the right n classifies."""
+    torch = torch_cuda()
+    rules = synth.make_rules(500, seed=33)
+    hdr = synth.make_packets(rules, 100, seed=34, frac_in=0.7)
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        d_hdr = to_dev(hdr)
+        d_out = torch.full((100,), -7, dtype=torch.int32, device="cuda")
+        s = torch.cuda.current_stream()
+        for args in [(d_hdr, d_out, 101), (d_hdr, d_out[:99], 100), (d_hdr, d_out[::2], 50)]:
+            with pytest.raises(ValueError):
+                T.tang_classify(rs, *args, s)
+        torch.cuda.synchronize()
+        assert (d_out.cpu().numpy() == -7).all()
+        T.tang_classify(rs, d_hdr, d_out, 100, s)
+        torch.cuda.synchronize()
+        assert np.array_equal(d_out.cpu().numpy().view(np.uint32), orc.classify(rules, hdr))
+        Ws, bs = train.random_weights(T.tang_ruleset_num_tuples(rs), 128, seed=1)
+        _load(rs, Ws, bs, "bf16", topk=2)
+        cand = torch.empty(150, dtype=torch.uint8, device="cuda")   # needs 100 x 2
+        with pytest.raises(ValueError):
+            T.tang_mlp_forward(rs, d_hdr, 100, None, cand, s)
+    finally:
+        T.tang_ruleset_destroy(rs)
+
+
 def test_empty_ruleset_answers_no_match():
     torch_cuda()
     rs = T.tang_ruleset_create(0, np.zeros(0, dtype=synth.RULE_DTYPE))
