@@ -442,6 +442,7 @@ int tang_classify_host(tang_ruleset_t* rs, const tang_header_t* hdr, uint32_t* r
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
     if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset cannot classify");
     if (n && (!hdr || !rule_id)) return fail(TANG_EINVAL, "NULL buffer");
+    if (n > SIZE_MAX / sizeof(tang_header_t)) return fail(TANG_EINVAL, "n too large");
     if (stats) std::memset(stats, 0, sizeof *stats);
     if (n == 0) return TANG_OK;
     TANG_HIP(hipSetDevice(rs->device));
