@@ -98,7 +98,7 @@ int tang_server_s::graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uin
         return TANG_OK;
     }
     if (g.exec) {
-        hipGraphExecDestroy(g.exec);
+        (void)hipGraphExecDestroy(g.exec);
         g.exec = nullptr;
     }
     StreamSlot& s = slots[si];
@@ -107,12 +107,12 @@ int tang_server_s::graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uin
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s.stream, &graph);
     if (rc) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return rc;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
         g.exec = nullptr;
         return hip_fail(e, "hipGraphInstantiate");
@@ -185,7 +185,7 @@ void tang_server_s::finish(StreamSlot& s, int status) {
 }
 
 void tang_server_s::loop() {
-    hipSetDevice(device);
+    (void)hipSetDevice(device);  // the ordinal was checked at creation
     for (;;) {
         bool progressed = false;
         for (auto& s : slots) {
@@ -249,15 +249,15 @@ void tang_server_s::loop() {
 }
 
 static void free_server(tang_server_t* srv) {
-    hipSetDevice(srv->device);
+    (void)hipSetDevice(srv->device);
     for (auto& kv : srv->graphs)
-        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     for (auto& s : srv->slots) {
-        if (s.stream) hipStreamSynchronize(s.stream);
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
         if (s.ev) (void)hipEventDestroy(s.ev);
         if (s.stream) (void)hipStreamDestroy(s.stream);
-        if (s.h_hdr) hipHostFree(s.h_hdr);
-        if (s.h_out) hipHostFree(s.h_out);
+        if (s.h_hdr) (void)hipHostFree(s.h_hdr);
+        if (s.h_out) (void)hipHostFree(s.h_out);
         if (s.d_hdr) (void)dev_release(s.d_hdr);
         if (s.d_out) (void)dev_release(s.d_out);
     }

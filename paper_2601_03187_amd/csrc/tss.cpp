@@ -503,7 +503,7 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
                                        (const uint32_t*)d_pos, (uint32_t)pos.size(), s);
     }
     hipError_t e2 = hipStreamSynchronize(s);
-    for (void* p : tmp) dev_release(p);
+    for (void* p : tmp) (void)dev_release(p);
     if (e != hipSuccess) return hip_fail(e, "update flush");
     if (e2 != hipSuccess) return hip_fail(e2, "update flush sync");
     return TANG_OK;
