@@ -137,10 +137,6 @@ def classify_definition(rules, pkts, live=None) -> np.ndarray:
     return out
 
 
-def rule_contains(rules_by_id: dict, rid: int, p) -> bool:
-    return rule_matches(rules_by_id[int(rid)], p)
-
-
 # ---------------------------------------------------------------------------------------
 # Model input: 104 header bits, MSB first, SIP(32) DIP(32) SP(16) DP(16) PROTO(8).
 
@@ -260,7 +256,10 @@ def mlp_forward(x: np.ndarray, Ws, bs, precision: str = "fp32", act_scales=None)
 
 
 def mlp_abs_forward(x: np.ndarray, Ws, bs) -> list:
-    """Per-layer magnitudes |W||a| + |b| used to bound rounding error (float64)."""
+    """Per-layer magnitudes m_l = |W_l| m_{l-1} + |b_l| with m_0 = |x| (float64). By the
+    triangle inequality m_l bounds |z_l| and |ReLU(z_l)| entrywise, so it scales the
+    accumulated rounding error of every layer; with non-negative weights, biases and
+    inputs it equals the forward pass itself."""
     a = np.abs(np.asarray(x, dtype=np.float64))
     mags = []
     for l, (W, b) in enumerate(zip(Ws, bs)):
@@ -307,7 +306,10 @@ def resnet_forward(s: np.ndarray, Ws, bs, precision: str = "bf16") -> np.ndarray
 
 
 def resnet_abs_forward(s: np.ndarray, Ws, bs) -> list:
-    """Magnitudes |W||a| + |b| (+ the residual's |x|) after every layer, for error bounds."""
+    """Magnitudes after every layer, for error bounds: m = |W_in| |s| + |b_in|, then per
+    block h = |w1| m + |b1| and m <- |w2| h + |b2| + m (the residual term enters with its
+    own magnitude), then |W_out| m + |b_out|. Returned in that order (input layer, the
+    two layers of each block, output layer)."""
     f64 = lambda a: np.abs(np.asarray(a, dtype=np.float64))  # noqa: E731
     a = f64(s) @ f64(Ws[0]).T + f64(bs[0])
     mags = [a]

@@ -291,20 +291,119 @@ def test_mlp_one_hot_selects_weight_column_and_relu_clips():
     assert orc.mlp_forward(x, [W1, W2, W3], b).tolist() == [[2.0, 0.0, 0.5]]
 
 
-def test_mlp_bf16_and_fp8_quantisation_steps():
-    # weights chosen off the bf16 grid: 1 + 2^-9 rounds to 1
-    W1 = np.full((1, 104), 0.0); W1[0, 0] = 1 + 2**-9
-    W2 = np.ones((1, 1)); W3 = np.ones((1, 1))
-    b = [np.zeros(1)] * 3
-    x = np.zeros((1, 104)); x[0, 0] = 1
-    assert orc.mlp_forward(x, [W1, W2, W3], b, "bf16")[0, 0] == 1.0
-    assert orc.mlp_forward(x, [W1, W2, W3], b, "fp32")[0, 0] == 1 + 2**-9
-    # fp8: layer-1 weight scale = amax/448, so the largest weight maps to 448 exactly
-    W1 = np.zeros((2, 104)); W1[0, 0] = 3.0; W1[1, 0] = 1.0
-    W2 = np.eye(2); W3 = np.eye(2)
-    b = [np.zeros(2)] * 3
-    out = orc.mlp_forward(x, [W1, W2, W3], b, "fp8", act_scales=[1.0, 3.0 / 448, 3.0 / 448])
-    assert np.allclose(out[0], [3.0, 1.0], rtol=2**-3)
+# --- Quantisation steps of the predictor (reading R19: BF16 round-to-nearest-even of the
+# weights and of every layer's input; FP8 E4M3 with a per-layer weight scale amax/448 and
+# static activation scales, FP32 accumulate and bias). Each case is worked out by hand
+# and isolates one step, so dropping or misplacing that step changes the pinned value.
+# The cases are shared with tests/test_oracle_mutants.py, which checks that a copy of the
+# oracle with each step broken fails at least one of them.
+
+def _one_hot_input():
+    x = np.zeros((1, 104))
+    x[0, 0] = 1.0
+    return x
+
+
+def mlp_quant_cases():
+    """(name, precision, Ws, bs, act_scales, exact logits) computed by hand."""
+    x = _one_hot_input()
+    cases = []
+    # BF16 weight rounding: 1 + 2^-9 is not a bfloat16 value (8 significant bits) and
+    # rounds to 1. It sits in the output layer, whose input (1) is exact, so no later
+    # rounding can hide a missing weight rounding.
+    W1 = np.zeros((1, 104)); W1[0, 0] = 1.0
+    cases.append(("bf16_weight", "bf16", [W1, np.ones((1, 1)), np.array([[1 + 2.0 ** -9]])],
+                  [np.zeros(1)] * 3, None, [1.0]))
+    # BF16 layer-input rounding, apart from the weights (all exact): the hidden value
+    # 1 + 2^-9 comes from an unrounded bias, the next layer reads it rounded to 1.
+    # The output bias 0.5 + 2^-10 is not a bfloat16 value (it would round to 0.5); it is
+    # added unrounded, and the logit 1.5 + 2^-10 is not rounded either (it would be 1.5).
+    cases.append(("bf16_input", "bf16", [W1, np.ones((1, 1)), np.ones((1, 1))],
+                  [np.array([2.0 ** -9]), np.zeros(1), np.array([0.5 + 2.0 ** -10])],
+                  None, [1.5 + 2.0 ** -10]))
+    # FP8 weight rounding, in the output layer: W1 column = [1, 1] and W2 = I scale to
+    # 448 (s_w = 1/448) and give hidden values [1, 1], which s_a = 1/448 maps to 448 (on
+    # the grid). W3 = diag(3, 1) has s_w = 3/448, so its scaled entries are 448 and
+    # 149.33; E4M3 has 144 and 160 in [128, 256) (step 16), so 149.33 -> 144 and the
+    # logits are 448 * 448 * (1/448) * (3/448) = 3 and 448 * 144 * ... = 27/28.
+    W1 = np.zeros((2, 104)); W1[:, 0] = 1.0
+    cases.append(("fp8_weight", "fp8", [W1, np.eye(2), np.diag([3.0, 1.0])], [np.zeros(2)] * 3,
+                  [1.0, 1.0 / 448, 1.0 / 448], [3.0, 27.0 / 28]))
+    # FP8 activation rounding: W1 column = [1, 0.5] scales to 448 and 224 (on the grid);
+    # a bias of 0.03 makes the second hidden value 0.53, which s_a = 1/448 maps to
+    # 237.44 -> 240 (grid 224, 240, 256): the next layers see 240/448 = 15/28.
+    # act_scales[0] is ignored, the input bits being exact: 3000 there changes nothing
+    # (read as a scale, 1/3000 would round to 0 in E4M3 and zero the first layer).
+    W1 = np.zeros((2, 104)); W1[0, 0] = 1.0; W1[1, 0] = 0.5
+    cases.append(("fp8_activation", "fp8", [W1, np.eye(2), np.eye(2)],
+                  [np.array([0.0, 0.03]), np.zeros(2), np.zeros(2)],
+                  [3000.0, 1.0 / 448, 1.0 / 448], [1.0, 15.0 / 28]))
+    # FP8 saturation: W1 column = [3, 0.25] scales to 448 and 37.33 -> 36 (grid 32, 36,
+    # 40), so the hidden values are 3 and 36 * 3/448 = 27/112. With s_a = 1/300 they
+    # map to 900, beyond the format's 448, which saturates to 448, and 72.32 -> 72 (grid
+    # 64, 72, 80): the next layers see 448/300 and 72/300.
+    W1 = np.zeros((2, 104)); W1[0, 0] = 3.0; W1[1, 0] = 0.25
+    cases.append(("fp8_saturate", "fp8", [W1, np.eye(2), np.eye(2)], [np.zeros(2)] * 3,
+                  [1.0, 1.0 / 300, 1.0 / 300], [448.0 / 300, 72.0 / 300]))
+    return x, cases
+
+
+def run_quant_case(fwd, x, case):
+    _, prec, Ws, bs, sc, _ = case
+    return fwd(x, Ws, bs, prec, act_scales=sc)[0]
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_mlp_quantisation_steps_hand_computed(k):
+    x, cases = mlp_quant_cases()
+    name, prec, Ws, bs, sc, want = cases[k]
+    got = run_quant_case(orc.mlp_forward, x, cases[k])
+    # the FP32 products of the stated scales (s_a s_w, 1/s) carry relative errors of a
+    # few 2^-24; nothing else is inexact
+    assert np.allclose(got, want, rtol=1e-6, atol=0), (name, got.tolist(), want)
+
+
+def test_mlp_fp32_path_takes_no_rounding():
+    x, cases = mlp_quant_cases()
+    _, _, Ws, bs, _, _ = cases[0]
+    assert orc.mlp_forward(x, Ws, bs, "fp32")[0, 0] == 1 + 2.0 ** -9
+    _, _, Ws, bs, _, _ = cases[1]
+    assert orc.mlp_forward(x, Ws, bs, "fp32")[0, 0] == 1.5 + 2.0 ** -9 + 2.0 ** -10
+
+
+# --- Magnitudes that set the GPU tests' error bounds -----------------------------------
+
+def test_mlp_abs_forward_equals_forward_on_nonnegative_networks():
+    """Closed form: with non-negative weights, biases and inputs no ReLU clips and no
+    absolute value changes anything, so every magnitude equals the layer's output."""
+    rng = np.random.default_rng(11)
+    dims = [104, 10, 9, 6]
+    Ws = [rng.random((dims[i + 1], dims[i])) for i in range(3)]
+    bs = [rng.random(dims[i + 1]) for i in range(3)]
+    x = rng.integers(0, 2, size=(8, 104)).astype(float)
+    mags = orc.mlp_abs_forward(x, Ws, bs)
+    a = x
+    for l in range(3):
+        a = a @ Ws[l].T + bs[l]
+        assert np.allclose(mags[l], a, rtol=1e-13, atol=0), l
+    assert np.allclose(mags[-1], orc.mlp_forward(x, Ws, bs), rtol=1e-13, atol=0)
+
+
+def test_mlp_abs_forward_hand_computed_mixed_signs():
+    """x = [1, -1]: m0 = [1, 1]. W1 = [[1, -2], [-1, 0]], b1 = [0.5, -3]:
+    m1 = [1 + 2 + 0.5, 1 + 0 + 3] = [3.5, 4] (the forward values are relu([3.5, -4]) =
+    [3.5, 0]: the magnitude is not |W a + b|). W2 = [[1, -1]], b2 = [-1]:
+    m2 = [3.5 + 4 + 1] = [8.5]. W3 = [[-2], [0.5]], b3 = [0.25, -0.25]:
+    m3 = [17.25, 4.5]."""
+    x = np.array([[1.0, -1.0]])
+    Ws = [np.array([[1.0, -2.0], [-1.0, 0.0]]), np.array([[1.0, -1.0]]), np.array([[-2.0], [0.5]])]
+    bs = [np.array([0.5, -3.0]), np.array([-1.0]), np.array([0.25, -0.25])]
+    mags = orc.mlp_abs_forward(x, Ws, bs)
+    assert [m.tolist() for m in mags] == [[[3.5, 4.0]], [[8.5]], [[17.25, 4.5]]]
+    z = orc.mlp_forward(x, Ws, bs)
+    # forward: h1 = relu([3.5, -4]) = [3.5, 0], h2 = relu([2.5]), z = [-4.75, 1.0]
+    assert z.tolist() == [[-4.75, 1.0]]
+    assert (np.abs(z) <= mags[-1]).all()
 
 
 def test_topk_ties_to_lower_index():

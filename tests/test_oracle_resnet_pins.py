@@ -94,6 +94,34 @@ def test_bf16_residual_is_the_rounded_block_input():
     assert orc.resnet_forward(s, Ws, bs, "fp32")[0, 0] == 1.0 + 2.0 ** -9
 
 
+def width_two_network():
+    """The hand-computed width-two network above (one block, three outputs)."""
+    s = np.zeros((1, 7))
+    s[0, 0] = 1.0
+    W_in = np.zeros((2, 7))
+    W_in[0, 0], W_in[1, 0] = 2.0, -1.0
+    Ws = [W_in, np.array([[1.0, 1.0], [0.0, -1.0]]), np.array([[0.5, 0.0], [1.0, -1.0]]),
+          np.array([[1.0, 0.0], [0.0, 1.0], [1.0, -1.0]])]
+    bs = [np.array([0.0, 3.0]), np.array([0.0, 1.0]), np.array([-1.0, 0.0]),
+          np.array([0.0, 0.0, 10.0])]
+    return s, Ws, bs
+
+
+# magnitudes of the width-two network, by hand: input layer |W_in| |s| + |b_in| =
+# [2, 0 + ... ] = [2, 1 + 3] = [2, 4]; block layer 1: [[1, 1], [0, 1]] [2, 4] + [0, 1] =
+# [6, 5]; block layer 2 plus the residual: [[0.5, 0], [1, 1]] [6, 5] + [1, 0] + [2, 4] =
+# [6, 15]; output: [[1, 0], [0, 1], [1, 1]] [6, 15] + [0, 0, 10] = [6, 15, 31]
+WIDTH_TWO_MAGS = [[[2.0, 4.0]], [[6.0, 5.0]], [[6.0, 15.0]], [[6.0, 15.0, 31.0]]]
+
+
+def test_magnitudes_hand_computed_width_two():
+    """Every magnitude of the width-two network, exactly (the logits [3, 6, 7] are
+    strictly inside them, so an over-estimate is caught as well as an under-estimate)."""
+    s, Ws, bs = width_two_network()
+    mags = orc.resnet_abs_forward(s, Ws, bs)
+    assert [m.tolist() for m in mags] == WIDTH_TWO_MAGS
+
+
 def test_magnitudes_bound_every_logit():
     rng = np.random.default_rng(5)
     Ws, bs = _model(32, 6, 7, rng)
