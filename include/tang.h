@@ -121,7 +121,11 @@ typedef struct tang_ruleset_s tang_ruleset_t;
 int tang_ruleset_create(int device, const tang_rule_t* rules, size_t n, tang_ruleset_t** out);
 void tang_ruleset_destroy(tang_ruleset_t* rs);
 
-/* Number of tuples C (the model's output width) and the signature of tuple t. */
+/*
+ * Number of tuples C (the model's output width, Sec. 6.1) and the signature of tuple t:
+ * its (SIP length, DIP length), tuples numbered by first appearance over the rules in
+ * ascending (priority, id) order as in Table 1 (Sec. 4.3). EINVAL for t >= C.
+ */
 uint32_t tang_ruleset_num_tuples(const tang_ruleset_t* rs);
 int tang_ruleset_tuple(const tang_ruleset_t* rs, uint32_t t, uint8_t* sip_len, uint8_t* dip_len);
 /* Number of live rules. */
@@ -144,16 +148,6 @@ int tang_ruleset_device_bytes(const tang_ruleset_t* rs, size_t* bytes);
 int tang_ruleset_set_stream(tang_ruleset_t* rs, void* stream);
 
 /*
- * Load predictor weights (deep copy). W[l] is a host pointer to dims[l+1] x dims[l]
- * floats, row-major [out][in] (PyTorch nn.Linear.weight); b[l] to dims[l+1] floats.
- * precision: FP32 (weights as given), BF16 (weights and each layer's input rounded to
- * bfloat16, nearest-even), FP8 (OCP E4M3, per-layer weight scale amax|W|/448 and
- * static per-layer activation scales act_scales[l] for l >= 1, act_scales[0] ignored
- * since the input bits are exact; inputs saturate at +-448). Accumulation is FP32 and
- * biases stay FP32 in every precision. act_scales must be NULL unless precision is FP8.
- * Replaces any previously loaded model. Without a model, classify probes all tuples.
- */
-/*
  * Drift of the tuple space under updates (Sec. 5.2.2): the number of live rules that an
  * insert placed in a tuple coarser than their own (SIP, DIP) length signature (restricted
  * insertion, Sec. 5.2.1), counted since the ruleset was built; a delete of such a rule
@@ -168,6 +162,17 @@ int tang_ruleset_coarse_rules(const tang_ruleset_t* rs, size_t* count);
  */
 int tang_ruleset_export(const tang_ruleset_t* rs, tang_rule_t* out, size_t cap, size_t* n);
 
+/*
+ * Load the predictor of Sec. 6.1 (plain form), weights deep-copied. W[l] is a host
+ * pointer to dims[l+1] x dims[l] floats, row-major [out][in] (PyTorch
+ * nn.Linear.weight); b[l] to dims[l+1] floats.
+ * precision: FP32 (weights as given), BF16 (weights and each layer's input rounded to
+ * bfloat16, nearest-even), FP8 (OCP E4M3, per-layer weight scale amax|W|/448 and
+ * static per-layer activation scales act_scales[l] for l >= 1, act_scales[0] ignored
+ * since the input bits are exact; inputs saturate at +-448). Accumulation is FP32 and
+ * biases stay FP32 in every precision. act_scales must be NULL unless precision is FP8.
+ * Replaces any previously loaded model. Without a model, classify probes all tuples.
+ */
 int tang_model_load(tang_ruleset_t* rs, const tang_mlp_desc_t* desc, const float* const* W,
                     const float* const* b, tang_precision_t precision, const float* act_scales);
 int tang_model_unload(tang_ruleset_t* rs);
@@ -198,7 +203,8 @@ int tang_model_load_resnet(tang_ruleset_t* rs, const tang_resnet_desc_t* desc,
                            tang_precision_t precision);
 
 /*
- * Classify n headers: d_rule_id[i] = id of the highest-priority live rule matching
+ * Classify n headers (Sec. 2.1 problem statement; the two stages of Sec. 5.1.1, with
+ * every answer certified): d_rule_id[i] = id of the highest-priority live rule matching
  * d_hdr[i], or TANG_NO_MATCH. d_hdr, d_rule_id: device pointers on the ruleset's GPU,
  * caller-owned, valid until the stream has passed this work. Asynchronous on `stream`
  * unless stats != NULL (then the counters are copied back and the call synchronises).
@@ -259,7 +265,12 @@ int tang_mlp_forward(tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n, f
  * fails with EEXIST on a live or repeated id and EINVAL on a bad field; delete fails
  * with ENOTFOUND on an id that is not live. The device changes are enqueued on the
  * ruleset's stream (tang_ruleset_set_stream); later classify calls on that stream see
- * them. rules/ids: host pointers.
+ * them. rules/ids: host pointers. An insert batch that would make one bucket list longer
+ * than 2^20 - 1 rules (what a hash slot can describe) fails with ENOMEM before any change.
+ * If the device part of an update fails (EDEVICE, or ENOMEM from a device allocation),
+ * the host side already holds the batch: the ruleset then refuses every later call that
+ * touches its device state with EDEVICE, and tang_ruleset_export still returns the live
+ * rules (this batch included) to rebuild from.
  */
 int tang_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n);
 int tang_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n);

@@ -17,8 +17,9 @@
  * special-cased).
  *
  * Method: sort the live rules by (priority, id), then scan each packet's rule list in
- * that order and stop at the first match ("compared one by one to return the
- * highest-priority matching rule", Sec. 5.1.1). Packets are split over POSIX threads.
+ * that order and stop at the first match, which is then the highest-priority match (the
+ * rules of a bucket are checked in turn in Sec. 5.1.1). Packets are split over POSIX
+ * threads.
  */
 #include <pthread.h>
 #include <stdint.h>

@@ -42,10 +42,21 @@ hipError_t dev_alloc(void** p, size_t bytes) {
     if (e != hipSuccess) return e;
     void* q = a.alloc(bytes, dev, a.ctx);
     if (!q) return hipErrorOutOfMemory;
-    std::lock_guard<std::mutex> lk(g_alloc_mu);
-    g_owned[q] = Owner{a.free, a.ctx, dev};
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        g_owned[q] = Owner{a.free, a.ctx, dev};
+    }
     *p = q;
-    return hipSuccess;
+    // A pool may hand out a block that work still queued on one of its streams uses (a
+    // caching allocator recycles a block once it is freed in that stream's order). The
+    // library writes the block on streams the pool knows nothing about, so the device
+    // must have finished that work first.
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)dev_release(q);
+    }
+    return e;
 }
 
 hipError_t dev_release(void* p) {
@@ -80,6 +91,13 @@ int fail(int code, const std::string& msg) {
 int hip_fail(hipError_t e, const char* what) {
     g_err = std::string(what) + ": " + hipGetErrorString(e);
     return TANG_EDEVICE;
+}
+
+// A ruleset whose last update could not be applied on the device refuses every call that
+// reads or changes its device state.
+static int refuse_failed() {
+    return fail(TANG_EDEVICE, "an earlier update of this ruleset failed on the device; destroy "
+                              "it and rebuild from tang_ruleset_export");
 }
 
 }  // namespace tang
@@ -203,6 +221,7 @@ int tang_ruleset_conflict_mask_words(tang_ruleset_t* rs, uint32_t id, uint32_t* 
     TANG_GUARD_BEGIN
     if (!rs || (n_words && !words)) return fail(TANG_EINVAL, "NULL argument");
     if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset has no masks");
+    if (rs->failed) return refuse_failed();
     auto it = rs->id2h.find(id);
     if (it == rs->id2h.end()) return fail(TANG_ENOTFOUND, "rule id is not live");
     TANG_HIP(hipSetDevice(rs->device));
@@ -264,6 +283,7 @@ int tang_model_load(tang_ruleset_t* rs, const tang_mlp_desc_t* desc, const float
     TANG_GUARD_BEGIN
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
     if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset cannot hold a model");
+    if (rs->failed) return refuse_failed();
     TANG_HIP(hipSetDevice(rs->device));
     TANG_HIP(hipDeviceSynchronize());  // no classify may still read the old weights
     return model_prepare(rs, desc, W, b, precision, act_scales);
@@ -275,6 +295,7 @@ int tang_model_load_resnet(tang_ruleset_t* rs, const tang_resnet_desc_t* desc, c
     TANG_GUARD_BEGIN
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
     if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset cannot hold a model");
+    if (rs->failed) return refuse_failed();
     TANG_HIP(hipSetDevice(rs->device));
     TANG_HIP(hipDeviceSynchronize());  // no classify may still read the old weights
     return resnet_prepare(rs, desc, W, b, precision);
@@ -297,6 +318,7 @@ int tang_model_unload(tang_ruleset_t* rs) {
 static int check_classify(const tang_ruleset_t* rs, const void* hdr, const void* out, size_t n) {
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
     if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset cannot classify");
+    if (rs->failed) return refuse_failed();
     if (n && (!hdr || !out)) return fail(TANG_EINVAL, "NULL buffer");
     if (((uintptr_t)hdr & 15u) != 0) return fail(TANG_EINVAL, "headers must be 16-byte aligned");
     if (((uintptr_t)out & 3u) != 0) return fail(TANG_EINVAL, "rule_id buffer must be 4-byte aligned");
@@ -441,6 +463,7 @@ int tang_classify_host(tang_ruleset_t* rs, const tang_header_t* hdr, uint32_t* r
     TANG_GUARD_BEGIN
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
     if (rs->device == TANG_HOST_ONLY) return fail(TANG_EINVAL, "host-only ruleset cannot classify");
+    if (rs->failed) return refuse_failed();
     if (n && (!hdr || !rule_id)) return fail(TANG_EINVAL, "NULL buffer");
     if (n > SIZE_MAX / sizeof(tang_header_t)) return fail(TANG_EINVAL, "n too large");
     if (stats) std::memset(stats, 0, sizeof *stats);
@@ -468,6 +491,7 @@ int tang_mlp_forward(tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n, f
     TANG_GUARD_BEGIN
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
     if (rs->device == TANG_HOST_ONLY || !rs->model.loaded) return fail(TANG_EINVAL, "no model loaded");
+    if (rs->failed) return refuse_failed();
     if (n && !d_hdr) return fail(TANG_EINVAL, "NULL headers");
     if (((uintptr_t)d_hdr & 15u) != 0) return fail(TANG_EINVAL, "headers must be 16-byte aligned");
     if (n == 0) return TANG_OK;
@@ -480,6 +504,7 @@ int tang_mlp_forward(tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n, f
 int tang_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
     TANG_GUARD_BEGIN
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    if (rs->failed) return refuse_failed();
     return apply_insert(rs, rules, n);
     TANG_GUARD_END
 }
@@ -487,6 +512,7 @@ int tang_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
 int tang_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n) {
     TANG_GUARD_BEGIN
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
+    if (rs->failed) return refuse_failed();
     return apply_delete(rs, ids, n);
     TANG_GUARD_END
 }

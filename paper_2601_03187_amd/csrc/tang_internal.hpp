@@ -54,9 +54,9 @@ constexpr int kMaskWords = 8;
 //   sp, dp   : lo | hi << 16 (inclusive)
 //   meta     : sip_len (bits 0-5) | dip_len (6-11) | proto (12-19) | exact-proto (20)
 //              | tuple (21-31)
-//   cmask    : conflict mask of a ruleset of at most 32 tuples (wider ones: side array)
-//   cmask    : conflict tuples -- tuples that hold a higher-priority rule whose box
-//              meets this rule's box (a superset after deletes)
+//   cmask    : conflict tuples of a ruleset of at most 32 tuples (wider ones: side
+//              array) -- tuples that hold a higher-priority rule whose box meets this
+//              rule's box (a superset after deletes)
 //   prio, id : the (priority, id) key; kDead marks a vacated record
 struct alignas(16) Rec {
     uint32_t sip, dip, sp, dp, meta, cmask, prio, id;
@@ -210,7 +210,7 @@ struct tang_ruleset_s {
         bool live;
     };
     struct Bucket {
-        uint32_t t, ms, md;             // t carries the sub-list kind in bits 5-7
+        uint32_t t, ms, md;             // t | kind << kKindShift (kind 0: main bucket)
         uint32_t slot;
         uint32_t off, cap;
         std::vector<uint32_t> members;  // rule handles in (priority, id) order
@@ -257,6 +257,7 @@ struct tang_ruleset_s {
     hipStream_t pipe_stream = nullptr;
     std::vector<hipEvent_t> pipe_events;
     uint64_t version = 0;   // bumped by every change that captured launches depend on
+    bool failed = false;    // an update's device flush failed: host and device disagree
 
     size_t device_bytes() const;
 };

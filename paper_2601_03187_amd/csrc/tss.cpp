@@ -35,14 +35,15 @@ uint32_t slot_insert(std::vector<Slot>& slots, const Slot& v) {
 
 bool is_main(const tang_ruleset_t::Bucket& bk) { return (bk.t >> kKindShift) == 0; }
 
-// Sub-list key of rule h inside the split main bucket b.
-tang_ruleset_t::BKey sub_key(const tang_ruleset_t* rs, uint32_t b, uint32_t h) {
-    const tang_rule_t& r = rs->rules[h].r;
-    const uint32_t t = rs->buckets[b].t;
+// Sub-list key of rule r inside the split main bucket b of tuple t.
+tang_ruleset_t::BKey sub_key_of(uint32_t t, uint32_t b, const tang_rule_t& r) {
     if (r.dp_lo == r.dp_hi) return {t | (kSubDp << kKindShift), b, r.dp_lo};
     if (r.sp_lo == r.sp_hi) return {t | (kSubSp << kKindShift), b, r.sp_lo};
     if (r.proto_mask) return {t | (kSubProto << kKindShift), b, r.proto};
     return {t | (kSubRest << kKindShift), b, 0u};
+}
+tang_ruleset_t::BKey sub_key(const tang_ruleset_t* rs, uint32_t b, uint32_t h) {
+    return sub_key_of(rs->buckets[b].t, b, rs->rules[h].r);
 }
 
 uint32_t find_or_add_bucket(tang_ruleset_t* rs, const tang_ruleset_t::BKey& k) {
@@ -509,6 +510,21 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
     return TANG_OK;
 }
 
+// The host mirror already holds a batch when its device flush runs; if the flush fails
+// (an allocation or a HIP call), host and device disagree, so the ruleset refuses every
+// later call that reads its device state (tang_ruleset_export still gives the live rules
+// a rebuild starts from).
+int flush_or_fail(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty,
+                  const std::vector<uint32_t>& fresh, bool rehash, bool filter_dirty) {
+    const int rc = flush(rs, dirty, fresh, rehash, filter_dirty);
+    if (rc) {
+        rs->failed = true;
+        return fail(rc, std::string("update not applied on the device (") + tang_last_error() +
+                            "); the ruleset is unusable, rebuild it from tang_ruleset_export");
+    }
+    return TANG_OK;
+}
+
 }  // namespace
 
 int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
@@ -517,19 +533,38 @@ int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
     // Validate the whole batch first (all-or-nothing).
     std::unordered_map<uint32_t, int> seen;
     auto sigs = rs->sigs;
+    // Every list must stay within what a slot can describe (kMaxBucketLen): each rule's
+    // destination list is bounded by its current length plus the batch's rules bound for
+    // it (a main bucket that splits during the batch only sheds rules into sub-lists).
+    std::unordered_map<tang_ruleset_s::BKey, size_t, tang_ruleset_s::BKeyHash> list_len;
     for (size_t i = 0; i < n; ++i) {
         int rc = validate_rule(rules[i]);
         if (rc) return rc;
         if (rs->id2h.count(rules[i].id) || !seen.emplace(rules[i].id, 1).second)
             return fail(TANG_EEXIST, "rule id " + std::to_string(rules[i].id) + " is live or repeated");
-        if (choose_tuple(sigs, rules[i].sip_len, rules[i].dip_len) < 0) {
+        int t = choose_tuple(sigs, rules[i].sip_len, rules[i].dip_len);
+        if (t < 0) {
             if (sigs.size() == (rs->nw == 1 ? 32u : (size_t)TANG_MAX_TUPLES))
                 return fail(TANG_EINVAL, rs->nw == 1
                                              ? "insert would need a 33rd tuple (the ruleset was built "
                                                "with one conflict-mask word)"
                                              : "insert would need a tuple beyond 256");
+            t = (int)sigs.size();
             sigs.emplace_back(rules[i].sip_len, rules[i].dip_len);
         }
+        const tang_rule_t r = normalise(rules[i]);
+        tang_ruleset_s::BKey key{(uint32_t)t, r.sip & pmask(sigs[t].first), r.dip & pmask(sigs[t].second)};
+        auto mb = rs->bucket_of.find(key);
+        if (mb != rs->bucket_of.end() && rs->buckets[mb->second].split)
+            key = sub_key_of((uint32_t)t, mb->second, r);
+        auto ins = list_len.emplace(key, 0);
+        if (ins.second) {
+            auto lb = rs->bucket_of.find(key);
+            if (lb != rs->bucket_of.end()) ins.first->second = rs->buckets[lb->second].members.size();
+        }
+        if (++ins.first->second > kMaxBucketLen)
+            return fail(TANG_ENOMEM, "insert would make a bucket list longer than " +
+                                         std::to_string(kMaxBucketLen) + " rules");
     }
     std::vector<uint32_t> dirty, fresh;
     std::vector<char> mark(rs->buckets.size() + n, 0);
@@ -583,7 +618,7 @@ int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
             filter_dirty = true;
         }
     }
-    return flush(rs, dirty, fresh, rehash, filter_dirty);
+    return flush_or_fail(rs, dirty, fresh, rehash, filter_dirty);
 }
 
 int apply_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n) {
@@ -607,7 +642,7 @@ int apply_delete(tang_ruleset_t* rs, const uint32_t* ids, size_t n) {
         if (rs->sigs[hr.tuple] != std::make_pair(hr.r.sip_len, hr.r.dip_len)) rs->n_coarse--;
         if (!mark[hr.bucket]) { mark[hr.bucket] = 1; dirty.push_back(hr.bucket); }
     }
-    return flush(rs, dirty, {}, false, false);
+    return flush_or_fail(rs, dirty, {}, false, false);
 }
 
 }  // namespace tang

@@ -4,8 +4,8 @@ This module only draws inputs. It holds none of the classification arithmetic (n
 matching, no tuple construction, no hashing), so both the GPU path and the CPU oracle
 can be fed from it without sharing any of the method's code.
 
-The paper measures on ClassBench-ng ACL/FW/IPC rulesets and on 1M-packet traces that
-"randomly match the rules" (Sec. 7.1). Those files are not available here; the
+The paper measures on ClassBench-ng ACL/FW/IPC rulesets and on 1M-packet synthetic
+traces whose packets fall inside randomly chosen rules (Sec. 7.1). Those files are not available here; the
 generator below stands in for them with the field shapes of the problem statement
 (Sec. 2.1: prefixes for the IPs, ranges for the ports, exact-or-wildcard protocol):
 

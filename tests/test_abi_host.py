@@ -267,3 +267,32 @@ def test_binding_checks_device_buffers():
         T._dbuf(np.zeros(4, dtype=np.uint32), 16, "d_rule_id")  # host memory
     assert T._dbuf(None, 16, "d_hdr") is None
     assert T._dbuf(0x1000, 1 << 40, "d_hdr") == 0x1000
+
+
+def test_insert_refuses_a_bucket_list_past_the_slot_length_field():
+    """A slot describes a list of at most 2^20 - 1 rules. An insert batch that would make
+    one list longer is refused as a whole (ENOMEM) before anything changes; one rule
+    fewer is accepted. All rules are catch-alls in one bucket of tuple (0, 0), whose
+    main bucket is split, so they share its last sub-list."""
+    base = np.zeros(40, dtype=synth.RULE_DTYPE)
+    base["id"] = np.arange(40)
+    base["priority"] = np.arange(40)
+    base["sp_hi"] = base["dp_hi"] = 0xFFFF
+    rs = T.tang_ruleset_create(T.TANG_HOST_ONLY, base)
+    try:
+        room = (1 << 20) - 1 - 40
+        big = np.zeros(room + 1, dtype=synth.RULE_DTYPE)
+        big["id"] = np.arange(100, 100 + room + 1)
+        big["priority"] = 100 + np.arange(room + 1)
+        big["sp_hi"] = big["dp_hi"] = 0xFFFF
+        with pytest.raises(T.TangError) as e:
+            T.tang_insert(rs, big)
+        assert e.value.name == "ENOMEM"
+        assert T.tang_ruleset_num_rules(rs) == 40
+        T.tang_insert(rs, big[:room])
+        assert T.tang_ruleset_num_rules(rs) == 40 + room
+        with pytest.raises(T.TangError) as e:
+            T.tang_insert(rs, big[room:])
+        assert e.value.name == "ENOMEM"
+    finally:
+        T.tang_ruleset_destroy(rs)

@@ -111,3 +111,83 @@ def test_serving_loop_slots_through_callers_allocator():
         assert not live, f"{len(live)} blocks not returned"
     finally:
         T.tang_set_allocator()
+
+
+def test_block_freed_on_a_busy_side_stream_is_not_written_early():
+    """torch's caching allocator recycles a block as soon as it is freed in its stream's
+    order, while work queued on that stream may still write it. Blocks freed on a busy
+    side stream, then taken by a ruleset build on that stream: the library waits for the
+    queued writes before filling its tables, so the answers are the oracle's."""
+    torch = torch_cuda()
+    talloc, tfree = T.torch_allocator()
+    T.tang_set_allocator(talloc, tfree)
+    side = torch.cuda.Stream()
+    rs = None
+    try:
+        rules = synth.make_rules(4000, seed=87)
+        hdr = synth.make_packets(rules, 20_000, seed=88, frac_in=0.8)
+        with torch.cuda.stream(side):
+            bufs = [torch.empty(1 << k, dtype=torch.uint8, device="cuda") for k in range(12, 25)]
+            a = torch.ones(4096, 4096, device="cuda")
+            c = torch.empty_like(a)
+            for _ in range(30):               # tens of ms of queued work on the side stream
+                torch.mm(a, a, out=c)
+            for buf in bufs:
+                buf.fill_(0xA5)               # runs after the products, into the freed blocks
+            del bufs, buf, a, c
+            rs = T.tang_ruleset_create(0, rules)
+            C = T.tang_ruleset_num_tuples(rs)
+            T.tang_model_load(rs, *train.random_weights(C, 128, seed=5), "bf16", topk=1)
+        torch.cuda.synchronize()
+        assert np.array_equal(classify_dev(rs, hdr), orc.classify(rules, hdr))
+    finally:
+        if rs is not None:
+            T.tang_ruleset_destroy(rs)
+        T.tang_set_allocator()
+
+
+def test_failed_update_flush_leaves_the_ruleset_refusing_device_calls():
+    """An insert whose device flush cannot allocate (the caller's allocator returns NULL
+    while the record array grows) fails, and since the host side already holds the batch,
+    the ruleset then refuses every device call (EDEVICE) instead of answering from tables
+    that disagree with it. Its export still gives the intended live rules, and a ruleset
+    rebuilt from them answers like the oracle."""
+    torch_cuda()
+    talloc, tfree = T.torch_allocator()
+    state = {"fail": False}
+
+    def alloc(nbytes, dev):
+        return 0 if state["fail"] else talloc(nbytes, dev)
+
+    T.tang_set_allocator(alloc, tfree)
+    rs = rs2 = None
+    try:
+        rules = synth.make_rules(3000, seed=89)
+        rs = T.tang_ruleset_create(0, rules)
+        hdr = synth.make_packets(rules, 5000, seed=90, frac_in=0.8)
+        assert np.array_equal(classify_dev(rs, hdr), orc.classify(rules, hdr))
+        ins = synth.make_rules(80_000, seed=91)   # more than the record array's spare room
+        ins["id"] += 1_000_000
+        state["fail"] = True
+        with pytest.raises(T.TangError) as e:
+            T.tang_insert(rs, ins)
+        assert e.value.name == "EDEVICE"
+        state["fail"] = False
+        for call in (lambda: classify_dev(rs, hdr), lambda: T.tang_delete(rs, rules["id"][:1]),
+                     lambda: T.tang_insert(rs, ins[:1]),
+                     lambda: T.tang_model_load(rs, *train.random_weights(
+                         T.tang_ruleset_num_tuples(rs), 128, seed=6), "bf16")):
+            with pytest.raises(T.TangError) as e:
+                call()
+            assert e.value.name == "EDEVICE"
+        every = np.concatenate([rules, ins])
+        exp = T.tang_ruleset_export(rs)
+        assert np.array_equal(np.sort(exp["id"]), np.sort(every["id"]))
+        rs2 = T.tang_ruleset_create(0, exp)
+        pk = synth.make_packets(every, 20_000, seed=92, frac_in=0.8)
+        assert np.array_equal(classify_dev(rs2, pk), orc.classify(every, pk))
+    finally:
+        for r in (rs, rs2):
+            if r is not None:
+                T.tang_ruleset_destroy(r)
+        T.tang_set_allocator()
