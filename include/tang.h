@@ -237,6 +237,19 @@ int tang_search_host(const tang_ruleset_t* rs, const tang_header_t* hdr, const u
 int tang_classify_host(tang_ruleset_t* rs, const tang_header_t* hdr, uint32_t* rule_id,
                        size_t n, tang_stats_t* stats);
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): tang_classify_host with the same
+ * arguments, results and statistics, except that the headers and rule ids are staged in
+ * a static device array the library holds on each GPU it runs on (5 MiB, kept until the
+ * process ends) instead of device blocks allocated per call, so the call allocates
+ * nothing. n is at most TANG_NOALLOC_MAX_HEADERS, else EINVAL. The batch is never split
+ * over two streams. Calls that overlap on one GPU (from several threads, on any
+ * rulesets) share the staging array and race: the caller serialises them.
+ */
+#define TANG_NOALLOC_MAX_HEADERS 262144u
+int tang_classify_host_noalloc(tang_ruleset_t* rs, const tang_header_t* hdr, uint32_t* rule_id,
+                               size_t n, tang_stats_t* stats);
+/*
  * The two stages of tang_classify, callable one by one (Sec. 5.1.1): tang_predict runs
  * the model and writes each header's candidate tuples into d_io[i] (one byte per
  * candidate, first candidate in the low byte); tang_search then probes, verifies and

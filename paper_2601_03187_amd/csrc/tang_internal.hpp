@@ -313,6 +313,8 @@ hipError_t launch_scatter_slots(Slot* d_slots, const uint32_t* d_idx, const Slot
 // Batches of at least two chunks of this many headers, with a BF16 or FP8 model and no
 // stats, are classified chunk by chunk with the model and the search on two streams.
 constexpr size_t kPipeChunk = (size_t)1 << 21;
+// Largest batch of tang_classify_host_noalloc (its static staging: 5 MiB per GPU).
+constexpr size_t kNoAllocMaxHeaders = (size_t)1 << 18;
 // tang_classify's body; allow_chunks = false keeps every launch on stream s (for callers
 // that capture the launches into a graph).
 int classify_async(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id, size_t n,

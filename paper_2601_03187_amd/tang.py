@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libtang.so")
 TANG_NO_MATCH = 0xFFFFFFFF
 TANG_HOST_ONLY = -1
 TANG_MAX_TUPLES = 256
+TANG_NOALLOC_MAX_HEADERS = 262144
 TANG_FP32, TANG_BF16, TANG_FP8 = 0, 1, 2
 PRECISIONS = {"fp32": TANG_FP32, "bf16": TANG_BF16, "fp8": TANG_FP8}
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOTFOUND", -4: "EEXIST", -5: "EDEVICE",
@@ -100,6 +101,8 @@ _sigs = {
     "tang_predict": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, _P]),
     "tang_search": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, _P, ctypes.POINTER(tang_stats_t)]),
     "tang_classify_host": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, ctypes.POINTER(tang_stats_t)]),
+    "tang_classify_host_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t,
+                                                  ctypes.POINTER(tang_stats_t)]),
     "tang_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P, _P]),
     "tang_insert": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "tang_delete": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
@@ -323,6 +326,20 @@ def tang_classify_host(rs: int, hdr: np.ndarray, want_stats: bool = False):
     _check(_lib.tang_classify_host(rs, h.ctypes.data if len(h) else None,
                                    out.ctypes.data if len(h) else None, len(h),
                                    ctypes.byref(st) if st is not None else None))
+    return (out, st.as_dict()) if want_stats else out
+
+
+def tang_classify_host_noalloc(rs: int, hdr: np.ndarray, want_stats: bool = False):
+    """tang_classify_host staged through the library's static device array (no device
+    allocation; at most TANG_NOALLOC_MAX_HEADERS headers per call)."""
+    h = np.ascontiguousarray(hdr)
+    if h.dtype != HDR_DTYPE:
+        raise TypeError("headers must use HDR_DTYPE")
+    out = np.empty(len(h), dtype=np.uint32)
+    st = tang_stats_t() if want_stats else None
+    _check(_lib.tang_classify_host_noalloc(rs, h.ctypes.data if len(h) else None,
+                                           out.ctypes.data if len(h) else None, len(h),
+                                           ctypes.byref(st) if st is not None else None))
     return (out, st.as_dict()) if want_stats else out
 
 
