@@ -77,6 +77,13 @@ def library_gather(dev, table_bytes: int) -> dict:
             "how": "torch advanced indexing, 4-byte elements"}
 
 
+def search_alg_bytes(slots: float, records: float, matched: float) -> float:
+    """Algorithmic bytes of the search per header: the 13-byte header, the 4-byte rule id,
+    16 bytes per hash slot read, 32 per rule record compared, and 4 for the conflict mask
+    of a matched rule."""
+    return 13 + 4 + 16 * slots + 32 * records + 4 * matched
+
+
 def pct(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
@@ -108,6 +115,11 @@ def main():
                          "stream on the 512k ruleset; c5: the serving loop over three rulesets; "
                          "c6: drifting updates with and without the deferred update")
     ap.add_argument("--rounds", type=int, default=100, help="c4: update rounds")
+    ap.add_argument("--update-sample", type=int, default=1000,
+                    help="c4: headers of each round's batch checked against the oracle's re-scan")
+    ap.add_argument("--skip-updates", action="store_true", help="skip the c4 update stream")
+    ap.add_argument("--skip-serving", action="store_true", help="skip the c5 serving loop")
+    ap.add_argument("--skip-drift", action="store_true", help="skip the c6 drift experiment")
     ap.add_argument("--requests", type=int, default=2000, help="c5: requests per load level")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run a plain device copy of this many bytes (3 times), the "
@@ -128,11 +140,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if args.workload == "c4":
-        return bench_updates(args)
+        return print_updates(bench_updates(args))
     if args.workload == "c5":
-        return bench_serving(args)
+        return print_serving(bench_serving(args))
     if args.workload == "c6":
-        return bench_drift(args)
+        return print_drift(bench_drift(args))
     if args.copy_bytes:
         a = torch.empty(args.copy_bytes // 4, dtype=torch.int32, device=dev).fill_(1)
         b = torch.empty_like(a)
@@ -200,7 +212,13 @@ def main():
         S = st["slots"] / n
         E = st["records"] / n
         F = st["filter_checks"] / n
-        bytes_pkt = 13 + 4 + 4 + 4 * F + 16 * S + 32 * E
+        matched = 1.0 - st["no_match"] / n
+        # algorithmic bytes of the search per header: header in, rule id out, the slots and
+        # records the method reads, and a matched rule's conflict mask; the bucket-filter
+        # words and the candidate word read back from the predictor are this
+        # implementation's own traffic, reported beside it
+        bytes_pkt = search_alg_bytes(S, E, matched)
+        impl_pkt = 4 * F + 4
         per[prec] = dict(
             mpps=n * args.steps / wall / 1e6, ms_per_step=wall * 1e3 / args.steps,
             p50_ms=pct(step_ms, 50), p99_ms=pct(step_ms, 99),
@@ -211,7 +229,8 @@ def main():
             probes_per_pkt=st["probes"] / n, slots_per_pkt=S, records_per_pkt=E,
             top1_hit_rate=st["top1_hits"] / n, fallback_rate=st["fallbacks"] / n,
             filter_checks_per_pkt=F, wave_steps=st["wave_steps"] / n,
-            wave_rounds=st["wave_rounds"] / n, search_bytes_per_pkt=bytes_pkt)
+            wave_rounds=st["wave_rounds"] / n, search_bytes_per_pkt=bytes_pkt,
+            search_overhead_bytes_per_pkt=impl_pkt, matched_rate=matched)
         # stage rooflines in Mpps: the predictor at its MFMA peak, the search at HBM peak
         # over its algorithmic bytes; serial = both back to back, overlap = the slower one
         k1_mpps = PEAK_TFLOPS[prec] * 1e12 / flop_pkt / 1e6
@@ -301,6 +320,22 @@ def main():
     if not args.skip_resnet:
         resnet = bench_resnet(args, rs, d_hdr, d_out, got_by_prec[base], C)
 
+    # the update stream (c4), the serving loop (c5) and the drift experiment (c6), each on
+    # its own rulesets; the headline ruleset's buffers are released first
+    upd = srv = drift = None
+    if not (args.skip_updates and args.skip_serving and args.skip_drift):
+        T.tang_model_unload(rs)
+        torch.cuda.empty_cache()
+    if not args.skip_updates:
+        upd = bench_updates(args)
+        log(f"[bench] c4: lookups {upd['lookup_mpps']['mean']:.0f} Mpps, update p50 "
+            f"{upd['update_ms']['p50']:.2f} ms p99 {upd['update_ms']['p99']:.2f} ms, "
+            f"{upd['bit_exact']['mismatches']} mismatches of {upd['bit_exact']['checked']}")
+    if not args.skip_serving:
+        srv = bench_serving(args)
+    if not args.skip_drift:
+        drift = bench_drift(args)
+
     # oracle: CPU baseline on a bounded seeded sample, and the bit-exact check
     cpu = None
     exact = None
@@ -343,7 +378,13 @@ def main():
                        "ms": head["k_mlp_ms"], "flop_per_pkt": flop_pkt},
              "k_classify": {"bound": "hbm", "achieved_gbs": head["search_gbs"],
                             "frac": head["search_gbs"] / PEAK_HBM_GBS, "ms": head["k_classify_ms"],
-                            "bytes_per_pkt": head["search_bytes_per_pkt"]}}
+                            "bytes_per_pkt": head["search_bytes_per_pkt"],
+                            "overhead_bytes_per_pkt": head["search_overhead_bytes_per_pkt"],
+                            "overhead": "bucket-filter words (4 B each) and the predictor's "
+                                        "candidate word (4 B), not counted in bytes_per_pkt"}}
+    tr = measured_traffic("k_classify", wl)
+    if tr:
+        other["k_classify"]["traffic_over_algorithmic"] = tr / (head["search_bytes_per_pkt"] * n)
     # the search's random accesses (filter words, slots, records: one line each) per second,
     # beside a plain library gather over a table of the same size
     acc_pkt = head["filter_checks_per_pkt"] + head["slots_per_pkt"] + head["records_per_pkt"]
@@ -375,6 +416,7 @@ def main():
         "per_precision": per, "candidate_change_vs_fp32": cand_change,
         "literal_ordering": lit, "no_model_probe_all": probe_all, "other_configs": configs,
         "paper_resnet_predictor": resnet, "paper_statistics": stats, "paper_cpu_gpu_split": hybrid,
+        "c4_updates": upd, "c5_serving": srv, "c6_drift": drift,
         "build_s": build_s, "train_top1": acc,
         "cpu_baseline": cpu,
         "paper_context": "TaNG reports 10.98 Mpps average at 512k rules (12 ClassBench-ng rulesets, "
@@ -742,6 +784,11 @@ def bench_drift(args):
             del d_hdr
         T.tang_ruleset_destroy(rs)
         res[mode] = {"windows": rows, "sample_mismatches": mism}
+    return res
+
+
+def print_drift(res):
+    import numpy as np
     line = {"metric": "c6 drifting updates: Mpps per window (1 MI355X)",
             "value": float(np.mean([r["mpps"] for r in res["with_deferred"]["windows"]])),
             "unit": "Mpps (mean over windows, with deferred update)", "n_gpus": 1,
@@ -779,6 +826,11 @@ def bench_updates(args):
     d_out = torch.empty(n, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
     lat, mpps, mism, checked = [], [], 0, 0
+    sample = args.update_sample
+    h_first = synth.make_packets(rules, n, seed=cfg["seed"] + 99, frac_in=cfg["frac_in"])
+    d_first = torch.from_numpy(h_first.view(np.uint8).reshape(-1)).cuda()
+    st0 = T.tang_classify(rs, d_first, d_out, n, stream, want_stats=True)
+    del d_first
     for rd, (ins, dels) in enumerate(ups):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -804,26 +856,34 @@ def bench_updates(args):
         torch.cuda.synchronize()
         mpps.append(n / a.elapsed_time(b) / 1e3)
         got = d_out.cpu().numpy().view(np.uint32)
-        samp = np.random.default_rng(rd).choice(n, 2000, replace=False)
+        samp = np.random.default_rng(rd).choice(n, sample, replace=False)
         mism += int((orc.classify(cat, hdr[samp], live=live) != got[samp]).sum())
         checked += len(samp)
         if rd % 10 == 0:
             log(f"[bench c4] round {rd}: update {lat[-1]:.2f} ms, lookup {mpps[-1]:.0f} Mpps")
     st = T.tang_classify(rs, d_hdr, d_out, n, stream, want_stats=True)
-    line = {"metric": "c4 update stream at 512k rules (1 MI355X)", "value": float(np.mean(mpps)),
-            "unit": "Mpps", "n_gpus": 1, "higher_is_better": True, "dtype": "bf16",
-            "data": "synthetic",
-            "config": {"workload": "c4_512k_updates: 524,288 rules, %d rounds x (100 inserts + 100 "
-                                   "deletes) + 1M-header lookups" % args.rounds},
-            "update_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat),
-                          "per": "100 inserts + 100 deletes, synchronised"},
-            "lookup_mpps": {"first": mpps[0], "last": mpps[-1], "min": min(mpps)},
-            "last_round": {"probes_per_pkt": st["probes"] / n, "records_per_pkt": st["records"] / n,
-                           "top1_hit_rate": st["top1_hits"] / n},
-            "bit_exact": {"sample_per_round": 2000, "checked": checked, "mismatches": mism,
-                          "bit_exact": mism == 0}}
-    print(json.dumps(line), flush=True)
+    res = {"workload": "c4_512k_updates: 524,288 rules, %d rounds x (100 inserts + 100 deletes) "
+                       "+ 1M-header lookups, BF16 predictor" % args.rounds,
+           "rounds": args.rounds,
+           "lookup_mpps": {"mean": float(np.mean(mpps)), "first": mpps[0], "last": mpps[-1],
+                           "min": min(mpps), "max": max(mpps), "per_round": mpps},
+           "update_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat),
+                         "per": "100 inserts + 100 deletes, synchronised"},
+           "before_updates": {"probes_per_pkt": st0["probes"] / n, "records_per_pkt": st0["records"] / n,
+                              "top1_hit_rate": st0["top1_hits"] / n, "train_top1": acc},
+           "last_round": {"probes_per_pkt": st["probes"] / n, "records_per_pkt": st["records"] / n,
+                          "top1_hit_rate": st["top1_hits"] / n},
+           "bit_exact": {"sample_per_round": sample, "checked": checked, "mismatches": mism,
+                         "bit_exact": mism == 0}}
     T.tang_ruleset_destroy(rs)
+    return res
+
+
+def print_updates(res):
+    line = {"metric": "c4 update stream at 512k rules (1 MI355X)", "value": res["lookup_mpps"]["mean"],
+            "unit": "Mpps", "n_gpus": 1, "higher_is_better": True, "dtype": "bf16",
+            "data": "synthetic", "config": {"workload": res["workload"]}, **res}
+    print(json.dumps(line), flush=True)
 
 
 def bench_serving(args):
@@ -891,17 +951,22 @@ def bench_serving(args):
         bad += int((T.tang_classify_host(sets[tag][1], hdr) != out).sum())
     for *_, r in reqs:
         T.tang_server_req_free(r)
-    line = {"metric": "c5 serving: p50/p99 request latency and Mpps (1 MI355X)",
-            "value": levels["75%"]["p99_ms"], "unit": "ms (p99 at 75% load)", "n_gpus": 1,
-            "higher_is_better": False, "dtype": "bf16", "data": "synthetic",
-            "config": {"workload": "c5_serving: rulesets of 10k/100k/512k rules, Poisson requests, "
-                                   "sizes log-uniform 32..65536, 4 streams, HIP graphs"},
-            "saturation": sat, "loads": levels,
-            "alone_vs_mix": {"requests_checked": 50, "mismatches": bad}}
-    print(json.dumps(line), flush=True)
+    res = {"workload": "c5_serving: rulesets of 10k/100k/512k rules, Poisson requests, sizes "
+                       "log-uniform 32..65536, 4 streams, HIP graphs, BF16 predictors",
+           "saturation": sat, "loads": levels,
+           "alone_vs_mix": {"requests_checked": 50, "mismatches": bad}}
     T.tang_server_destroy(srv)
     for _, rs, _ in sets:
         T.tang_ruleset_destroy(rs)
+    return res
+
+
+def print_serving(res):
+    line = {"metric": "c5 serving: p50/p99 request latency and Mpps (1 MI355X)",
+            "value": res["loads"]["75%"]["p99_ms"], "unit": "ms (p99 at 75% load)", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": res["workload"]}, **res}
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

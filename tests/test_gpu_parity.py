@@ -204,32 +204,52 @@ def test_chunked_two_stream_classify_equals_oracle():
         T.tang_ruleset_destroy(rs)
 
 
-def test_c3_512k_rules_16m_headers_sampled():
-    """512k rules, 16,777,216 Zipf headers, BF16 and FP8, in the launch shape the
-    benchmark times: every answer's key is <= the key of the rule the header was drawn
-    from (an answer at least as good exists) and the answer rule contains the header; a
-    seeded sample of 20,000 answers equals the oracle's."""
+def _c3_sampled(ordering, precs, sample_seed):
+    """512k rules in the given order, 16,777,216 Zipf headers, in the launch shape the
+    benchmark times (chunked over two streams for BF16 / FP8): every answer's key is <=
+    the key of the rule the header was drawn from (an answer at least as good exists),
+    every answer is a rule, the answer rule contains the header on a sample, and a seeded
+    sample of 20,000 answers equals the oracle's. The same answers in every precision."""
     torch = torch_cuda()
     cfg = synth.CONFIGS["c3_512k"]
-    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering="specificity")
+    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering=ordering)
+    assert np.array_equal(rules["id"], np.arange(len(rules)))  # id == index below
     hdr, src = synth.make_packets(rules, cfg["n_pkts"], seed=cfg["seed"] + 1,
                                   frac_in=cfg["frac_in"], zipf_s=cfg["zipf"], return_src=True)
     rs = T.tang_ruleset_create(0, rules)
     try:
-        samp = np.random.default_rng(5).choice(len(hdr), 20_000, replace=False)
+        samp = np.random.default_rng(sample_seed).choice(len(hdr), 20_000, replace=False)
         want = orc.classify(rules, hdr[samp])
         Ws, bs, sc, acc = train.fit(rs, rules, hdr[:200_000], 256, steps=200, seed=4, device="cuda")
-        for prec in ("bf16", "fp8"):
+        first = None
+        bound = keys_of(rules, rules["id"][src])
+        for prec in precs:
+            print(f"c3 {ordering} {prec}: {len(hdr)} headers", flush=True)
             _load(rs, Ws, bs, prec, sc=sc)
             got = classify_dev(rs, hdr)
             assert np.array_equal(got[samp], want), prec
             assert (got != NO).all()
-            assert (keys_of(rules, got) <= keys_of(rules, rules["id"][src])).all()
+            assert (keys_of(rules, got) <= bound).all()
             for k in samp[:200]:
-                assert orc.rule_matches(rules[int(got[k])], hdr[k])  # id == index here
+                assert orc.rule_matches(rules[int(got[k])], hdr[k])
+            if first is None:
+                first = got
+            else:
+                assert np.array_equal(got, first), prec
         del torch
     finally:
         T.tang_ruleset_destroy(rs)
+
+
+def test_c3_512k_rules_16m_headers_sampled():
+    """The benchmark workload (specificity order) in BF16, FP8 and FP32."""
+    _c3_sampled("specificity", ("bf16", "fp8", "fp32"), 5)
+
+
+def test_c3_512k_literal_order_16m_headers_sampled():
+    """The same 512k-rule generator in literal order (catch-all rules early shadow most
+    later rules: long certification, many tuples per header), BF16 and FP32."""
+    _c3_sampled("literal", ("bf16", "fp32"), 6)
 
 
 def test_empty_and_ragged_batches():

@@ -115,3 +115,43 @@ def test_rulesets_added_while_serving():
         T.tang_server_destroy(srv)
         for _, rs in sets:
             T.tang_ruleset_destroy(rs)
+
+
+def test_alone_equals_mix_at_serving_sizes():
+    """The serving workload's shape: resident rulesets of 10,000, 100,000 and 524,288
+    rules with BF16 predictors, requests of log-uniform size 32..65,536 with a uniform
+    ruleset tag, submitted in bursts while earlier ones run, 4 streams, graphs: every
+    answer of every request equals the same headers classified alone, and a seeded
+    sample of each request equals the oracle's."""
+    torch_cuda()
+    cfg = synth.CONFIGS["c5_serving"]
+    sets = []
+    for k, n_rules in enumerate(cfg["sizes"]):
+        rules = synth.make_rules(n_rules, seed=cfg["seed"] + k, ordering="specificity")
+        rs = T.tang_ruleset_create(0, rules)
+        C = T.tang_ruleset_num_tuples(rs)
+        Ws, bs = train.random_weights(C, cfg["hidden"], seed=50 + k)
+        T.tang_model_load(rs, Ws, bs, "bf16")
+        sets.append((rules, rs))
+    srv = T.tang_server_create(0, n_streams=4, max_batch=65536, use_graphs=1)
+    try:
+        tags = [T.tang_server_add_ruleset(srv, rs) for _, rs in sets]
+        _, sizes, tg = synth.make_requests(120, len(sets), seed=77, rate_per_s=1.0)
+        reqs = []
+        for q in range(len(sizes)):
+            hdr = synth.make_packets(sets[tg[q]][0], int(sizes[q]), seed=3000 + q, frac_in=cfg["frac_in"])
+            out = np.full(len(hdr), 0xDEADBEEF, dtype=np.uint32)
+            reqs.append((int(tg[q]), hdr, out, T.tang_server_submit(srv, tags[tg[q]], hdr, out)))
+            if q % 10 == 9:
+                time.sleep(0.002)
+        rng = np.random.default_rng(78)
+        for tag, hdr, out, r in reqs:
+            T.tang_server_wait(r, 120_000_000)
+            assert np.array_equal(out, T.tang_classify_host(sets[tag][1], hdr)), tag
+            k = rng.choice(len(hdr), size=min(len(hdr), 300), replace=False)
+            assert np.array_equal(out[k], orc.classify(sets[tag][0], hdr[k])), tag
+            T.tang_server_req_free(r)
+    finally:
+        T.tang_server_destroy(srv)
+        for _, rs in sets:
+            T.tang_ruleset_destroy(rs)
