@@ -7,15 +7,18 @@
 //      remaining tuple (the paper's post-verification search, Sec. 5.1.1); in both
 //      cases a tuple whose best (lowest) key cannot beat the current answer is skipped.
 // Before any slot walk, a bit of the bucket filter rules out a tuple that has no bucket
-// for the header's masked addresses. Certification first sweeps the filter for all of a
-// packet's remaining tuples, eight independent loads at a time, and then each lane walks
-// slots only for its own tuples whose bit is set. Both halves matter on a 64-lane wave:
-// one dependent L2 round trip per tuple would cost two dozen round trips back to back,
-// and a wave-uniform loop over tuples would pay for the union of all lanes' tuples.
+// for the header's masked addresses. The filter is blocked by prefix group (the tuples
+// sharing their longer field's length): one 8-byte block answers every tuple of its
+// group, so certification loads one block per group it needs -- all of them at once,
+// eight independent loads at a time -- and then each lane walks slots only for its own
+// tuples whose bit is set. Random loads are what the search pays for (each one costs
+// an L2 request whatever its width), so the scan also reads only the first half of each
+// record and the second half only when a rule matches.
 // Candidates come packed in the output word (one byte per candidate) from the MLP.
 // Tuple spaces of more than 32 tuples (up to 256) use the same steps over eight-word
-// tuple masks, with conflict masks in a side array, a pre-check of the header's field
-// keys before the filter sweep, and per-lane filter batches.
+// tuple masks, with conflict masks in a side array.
+#include <type_traits>
+
 #include "tang_internal.hpp"
 
 namespace tang {
@@ -31,50 +34,51 @@ __device__ __forceinline__ bool kless(uint32_t p1, uint32_t i1, uint32_t p2, uin
     return p1 < p2 || (p1 == p2 && i1 < i2);
 }
 
-__device__ __forceinline__ bool rec_match(const Rec& r, uint32_t sip, uint32_t dip, uint32_t sp,
-                                          uint32_t dp, uint32_t proto) {
-    const uint32_t m = r.meta;
-    const uint32_t sm = pmask(meta_sl(m)), dm = pmask(meta_dl(m));
-    bool ok = (((sip ^ r.sip) & sm) == 0) & (((dip ^ r.dip) & dm) == 0);
-    ok &= (sp >= (r.sp & 0xFFFFu)) & (sp <= (r.sp >> 16));
-    ok &= (dp >= (r.dp & 0xFFFFu)) & (dp <= (r.dp >> 16));
-    ok &= (meta_exact(m) == 0) | (proto == meta_proto(m));
-    return ok;
-}
-
-// Whole-record and whole-slot loads (two and one 16-byte loads). Copying the structs
-// field by field lets the compiler split them into narrow loads sunk into the branches
-// that use each field: more load instructions per wave and dependent round trips
-// between them (priority and id first, the rest after the comparison).
-// An empty asm that takes all four words keeps each 16-byte load whole and in place.
+// Whole 16-byte loads. Copying the structs field by field lets the compiler split them
+// into narrow loads sunk into the branches that use each field: more load instructions
+// per wave and dependent round trips between them. An empty asm that takes all four
+// words keeps each 16-byte load whole and in place.
 __device__ __forceinline__ uint4 load16(const void* p) {
     uint4 a = *reinterpret_cast<const uint4*>(p);
     asm volatile("" : "+v"(a.x), "+v"(a.y), "+v"(a.z), "+v"(a.w));
     return a;
 }
-__device__ __forceinline__ Rec load_rec(const Rec* p) {
-    const uint4 a = load16(p), c = load16(reinterpret_cast<const uint4*>(p) + 1);
-    return Rec{a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
-}
 __device__ __forceinline__ Slot load_slot(const Slot* p) {
     const uint4 a = load16(p);
     return Slot{a.x, a.y, a.z, a.w};
 }
+__device__ __forceinline__ uint2 load8(const uint2* p) {
+    uint2 a = *p;
+    asm volatile("" : "+v"(a.x), "+v"(a.y));
+    return a;
+}
 
 // Compares one list of records in (priority, id) order: the first match is its best;
 // the scan stops there or at the first record that cannot beat the current answer.
+// The hot half (ports, priority, protocol/lengths) decides; the cold half (prefixes,
+// id, conflict mask) is read for a priority tie, a rule held by a coarser tuple, and
+// the match.
 template <bool STATS>
-__device__ __forceinline__ void scan_list(uint32_t off, uint32_t len, uint32_t sip, uint32_t dip,
-                                          uint32_t sp, uint32_t dp, uint32_t proto,
+__device__ __forceinline__ void scan_list(uint32_t t, uint32_t off, uint32_t len, uint32_t sip,
+                                          uint32_t dip, uint32_t sp, uint32_t dp, uint32_t proto,
                                           const Rec* __restrict__ recs, Best& b, uint32_t& n_recs) {
     for (uint32_t k = 0; k < len; ++k) {
-        const Rec r = load_rec(recs + off + k);
+        const uint4* p = reinterpret_cast<const uint4*>(recs + off + k);
+        const uint4 h = load16(p);  // sp, dp, prio, meta
         if (STATS) ++n_recs;
-        if (!kless(r.prio, r.id, b.prio, b.id)) break;
-        if (rec_match(r, sip, dip, sp, dp, proto)) {
-            b = Best{r.prio, r.id, r.cmask, meta_tuple(r.meta), off + k};
-            break;
+        if (h.z > b.prio) break;
+        bool ok = (sp >= (h.x & 0xFFFFu)) & (sp <= (h.x >> 16)) & (dp >= (h.y & 0xFFFFu)) &
+                  (dp <= (h.y >> 16)) & ((meta_exact(h.w) == 0) | (proto == meta_proto(h.w)));
+        if (!ok && h.z < b.prio) continue;
+        const uint4 c = load16(p + 1);  // sip, dip, id, cmask
+        if (h.z == b.prio && !(c.z < b.id)) break;
+        if (!ok) continue;
+        if (meta_check(h.w)) {
+            const uint32_t sm = pmask(meta_sl(h.w)), dm = pmask(meta_dl(h.w));
+            if (((sip ^ c.x) & sm) | ((dip ^ c.y) & dm)) continue;
         }
+        b = Best{h.z, c.z, c.w, t, off + k};
+        break;
     }
 }
 
@@ -95,20 +99,20 @@ __device__ __forceinline__ Slot find_slot(uint64_t h64, uint32_t tk, uint32_t k0
     return Slot{0, 0, kEmptyTL, 0};
 }
 
-// Searches tuple t for this header (its masked key and hash given): the slot walk to the
-// bucket, then the bucket's list, or for a split bucket the sub-lists the header selects.
+// Searches tuple t for this header: the slot walk to the bucket, then the bucket's list,
+// or for a split bucket the sub-lists the header selects.
 template <bool STATS>
-__device__ __forceinline__ void search_tuple(uint32_t t, uint64_t h, uint32_t ms, uint32_t md,
-                                             uint32_t sip, uint32_t dip, uint32_t sp, uint32_t dp,
-                                             uint32_t proto, uint32_t slot_mask,
-                                             const Slot* __restrict__ slots,
+__device__ __forceinline__ void search_tuple(uint32_t t, const TupleDev* s_t, uint32_t sip,
+                                             uint32_t dip, uint32_t sp, uint32_t dp, uint32_t proto,
+                                             uint32_t slot_mask, const Slot* __restrict__ slots,
                                              const Rec* __restrict__ recs, Best& b,
                                              uint32_t& n_probe, uint32_t& n_slots, uint32_t& n_recs) {
     if (STATS) ++n_probe;
-    const Slot s = find_slot<STATS>(h, t, ms, md, slot_mask, slots, n_slots);
+    const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
+    const Slot s = find_slot<STATS>(key_hash(t, ms, md), t, ms, md, slot_mask, slots, n_slots);
     if (s.tl == kEmptyTL) return;
     if (!(s.off & kSplit)) {
-        scan_list<STATS>(s.off, s.tl & kMaxBucketLen, sip, dip, sp, dp, proto, recs, b, n_recs);
+        scan_list<STATS>(t, s.off, s.tl & kMaxBucketLen, sip, dip, sp, dp, proto, recs, b, n_recs);
         return;
     }
     // a split bucket: only the four sub-lists this header's DP, SP and protocol select
@@ -120,25 +124,24 @@ __device__ __forceinline__ void search_tuple(uint32_t t, uint64_t h, uint32_t ms
         const Slot u = find_slot<STATS>(key_hash(tk, bi, keys[q][1]), tk, bi, keys[q][1], slot_mask,
                                         slots, n_slots);
         if (u.tl != kEmptyTL)
-            scan_list<STATS>(u.off, u.tl & kMaxBucketLen, sip, dip, sp, dp, proto, recs, b, n_recs);
+            scan_list<STATS>(t, u.off, u.tl & kMaxBucketLen, sip, dip, sp, dp, proto, recs, b, n_recs);
     }
 }
 
-// Searches tuple t for this header after checking its filter bit.
-template <bool STATS>
-__device__ __forceinline__ void probe(uint32_t t, uint32_t sip, uint32_t dip, uint32_t sp,
-                                      uint32_t dp, uint32_t proto, const TupleDev* s_t,
-                                      uint32_t slot_mask, uint32_t filter_mask,
-                                      const uint32_t* __restrict__ filter,
-                                      const Slot* __restrict__ slots, const Rec* __restrict__ recs,
-                                      Best& b, uint32_t& n_probe, uint32_t& n_slots,
-                                      uint32_t& n_recs, uint32_t& n_filter) {
-    const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
-    const uint32_t bit = filter_hash(t, ms, md) & filter_mask;
-    if (STATS) ++n_filter;
-    if (!((filter[bit >> 5] >> (bit & 31u)) & 1u)) return;
-    search_tuple<STATS>(t, key_hash(t, ms, md), ms, md, sip, dip, sp, dp, proto, slot_mask, slots,
-                        recs, b, n_probe, n_slots, n_recs);
+// The filter block of group key gk for this header.
+__device__ __forceinline__ const uint2* block_of(const uint2* __restrict__ filter, uint32_t gk,
+                                                 uint32_t sip, uint32_t dip, uint32_t filter_mask) {
+    const uint32_t len = gk & 63u;
+    const uint32_t v = (gk & 64u ? dip : sip) & pmask(len);
+    return filter + (filter_block(gk, v) & filter_mask);
+}
+
+// Whether tuple t of group key gk may hold a bucket for this header, given its block.
+__device__ __forceinline__ bool block_has(uint2 blk, uint32_t t, uint32_t gk, const TupleDev* s_t,
+                                          uint32_t sip, uint32_t dip) {
+    const uint32_t o = gk & 64u ? (sip & s_t[t].smask) : (dip & s_t[t].dmask);
+    const uint32_t bit = filter_bit(t, o);
+    return ((bit & 32u ? blk.y : blk.x) >> (bit & 31u)) & 1u;
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
@@ -161,49 +164,49 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 }
 
 // NW: conflict-mask words (1 for at most 32 tuples, kMaskWords for up to 256). Tuple
-// sets are NW-word bit masks (word t / 32, bit t % 32); everything else is as for one word.
-template <bool STATS, int NW, bool RANKED>
+// sets are NW-word bit masks (word t / 32, bit t % 32); group sets one word (at most 32
+// groups) or two (64).
+template <bool STATS, int NW>
 __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                                                   uint32_t* __restrict__ out, uint32_t n,
                                                   const Slot* __restrict__ slots,
                                                   const Rec* __restrict__ recs,
                                                   const uint32_t* __restrict__ cmask_rows,
-                                                  const uint32_t* __restrict__ filter,
+                                                  const uint2* __restrict__ filter,
                                                   const TupleTable* __restrict__ ttg, int kcand,
                                                   StatsDev* __restrict__ st) {
     constexpr uint32_t NT = 32u * NW;
+    constexpr int NG = NW == 1 ? 32 : kMaxGroups;   // groups: at most one per tuple
+    using GMask = typename std::conditional<NW == 1, uint32_t, unsigned long long>::type;
     __shared__ TupleDev s_t[NT];
     __shared__ uint2 s_rank[NT];  // best keys in ascending order
-    __shared__ uint32_t s_order[NT];  // tuple indices in that order
     __shared__ uint32_t s_prefix[NT + 1][NW];
-    __shared__ uint32_t s_all[NW];
+    __shared__ uint32_t s_all[NW], s_nog[NW];
+    __shared__ uint32_t s_gid[NT];
+    __shared__ uint32_t s_gkey[NG];
+    __shared__ uint32_t s_gmask[NG][NW];
     __shared__ uint32_t s_misc[4];
-    // field pre-check (wide tuple spaces only): distinct lengths and their tuple masks
-    constexpr int NF = NW > 1 ? 33 : 1;
-    __shared__ uint32_t s_flen[2][NF];
-    __shared__ uint32_t s_fmask[2][NF][NW];
-    __shared__ uint32_t s_nflen[2];
     const int tid = threadIdx.x;
     for (uint32_t k = tid; k < NT; k += 256u) {
         s_t[k] = ttg->t[k];
         s_rank[k] = make_uint2(ttg->rank_prio[k], ttg->rank_id[k]);
-        s_order[k] = ttg->order[k];
+        s_gid[k] = ttg->gid[k];
     }
     for (uint32_t k = tid; k < (NT + 1) * NW; k += 256u) s_prefix[k / NW][k % NW] = ttg->prefix[k / NW][k % NW];
-    if (tid < NW) s_all[tid] = ttg->all_mask[tid];
-    if constexpr (NW > 1) {
-        for (uint32_t k = tid; k < 2u * NF * NW; k += 256u)
-            s_fmask[k / (NF * NW)][(k / NW) % NF][k % NW] = ttg->fmask[k / (NF * NW)][(k / NW) % NF][k % NW];
-        if (tid < 2 * NF) s_flen[tid / NF][tid % NF] = ttg->flen[tid / NF][tid % NF];
-        if (tid < 2) s_nflen[tid] = ttg->nflen[tid];
+    for (uint32_t k = tid; k < (uint32_t)NG * NW; k += 256u) s_gmask[k / NW][k % NW] = ttg->gmask[k / NW][k % NW];
+    if (tid < NG) s_gkey[tid] = ttg->gkey[tid];
+    if (tid < NW) {
+        s_all[tid] = ttg->all_mask[tid];
+        s_nog[tid] = ttg->nogroup[tid];
     }
     if (tid == 0) {
         s_misc[0] = ttg->n;
+        s_misc[1] = ttg->ngroups;
         s_misc[2] = ttg->slot_mask;
         s_misc[3] = ttg->filter_mask;
     }
     __syncthreads();
-    const uint32_t ntup = s_misc[0], slot_mask = s_misc[2], filter_mask = s_misc[3];
+    const uint32_t ntup = s_misc[0], ngroups = s_misc[1], slot_mask = s_misc[2], filter_mask = s_misc[3];
     const uint32_t i = blockIdx.x * 256u + tid;
     uint32_t n_probe = 0, n_slots = 0, n_recs = 0, top1 = 0, fb = 0, nm = 0, active = 0;
     uint32_t n_filter = 0, n_steps = 0, n_rounds = 0;
@@ -212,6 +215,9 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
 #pragma unroll
     for (int w = 0; w < NW; ++w) todo[w] = 0;
     Best b{kDead, kDead, 0u, 0u, 0u};
+    // the first candidate's group block, kept for the other tuples of its group
+    uint32_t g0 = kNoGroup;
+    uint2 blk0 = make_uint2(0u, 0u);
     if (i < n) {
         active = 1;
         const uint4 h = hdr[i];
@@ -234,8 +240,26 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                 if ((pw >> (t & 31u)) & 1u) continue;
                 pw |= 1u << (t & 31u);
                 if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) continue;
-                probe<STATS>(t, sip, dip, sp, dp, proto, s_t, slot_mask, filter_mask, filter, slots,
-                             recs, b, n_probe, n_slots, n_recs, n_filter);
+                const uint32_t g = s_gid[t];
+                bool pass = true;
+                if (g != kNoGroup) {
+                    const uint32_t gk = s_gkey[g];
+                    uint2 blk;
+                    if (g == g0) {
+                        blk = blk0;
+                    } else {
+                        blk = load8(block_of(filter, gk, sip, dip, filter_mask));
+                        if (STATS) ++n_filter;
+                    }
+                    if (g0 == kNoGroup) {
+                        g0 = g;
+                        blk0 = blk;
+                    }
+                    pass = block_has(blk, t, gk, s_t, sip, dip);
+                }
+                if (pass)
+                    search_tuple<STATS>(t, s_t, sip, dip, sp, dp, proto, slot_mask, slots, recs, b,
+                                        n_probe, n_slots, n_recs);
             }
             found = b.id != kDead;
         }
@@ -272,189 +296,70 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
             for (int w = 0; w < NW; ++w) todo[w] &= s_prefix[k][w];
         }
     }
-    // Wide tuple spaces, headers with many tuples left (all that matched nothing yet, and
-    // those with a wide conflict mask): check the field keys of the distinct lengths of
-    // each field (eight loads at a time) and keep only the tuples whose SIP and DIP
-    // lengths both passed. Below 25 tuples three more batches would not pay.
-    if constexpr (NW > 1) {
-        uint32_t left = 0;
+    // Phase 1: the groups the remaining tuples need (the first candidate's block is
+    // already here), their blocks eight at a time per lane, then each needed tuple's bit.
+    uint32_t hits[NW];
+    GMask gneed = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) left += __builtin_popcount(todo[w]);
-        const bool many = left > 24u;
-        if (wave_or(many ? 1u : 0u)) {
-            unsigned long long pass[2] = {0ull, 0ull};
+    for (int w = 0; w < NW; ++w) hits[w] = todo[w] & s_nog[w];
+    if (g0 != kNoGroup) {
 #pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                const uint32_t nl = s_nflen[side], v = side == 0 ? sip : dip;
-                for (uint32_t i0 = 0; i0 < nl; i0 += 8) {
-                    if (STATS) ++n_rounds;
-                    uint32_t wd[8], pos[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        wd[q] = 0;
-                        pos[q] = 0;
-                        if (many && i0 + q < nl) {
-                            const uint32_t len = s_flen[side][i0 + q];
-                            const uint32_t bit = field_filter_hash(side, len, v & pmask(len)) & filter_mask;
-                            wd[q] = filter[bit >> 5];
-                            pos[q] = bit & 31u;
-                            if (STATS) ++n_filter;
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        pass[side] |= (unsigned long long)((wd[q] >> pos[q]) & 1u) << (i0 + q);
-                }
-            }
-            if (many) {
-                uint32_t keep[2][NW];
-#pragma unroll
-                for (int side = 0; side < 2; ++side) {
-#pragma unroll
-                    for (int w = 0; w < NW; ++w) keep[side][w] = 0;
-                    for (unsigned long long m = pass[side]; m; m &= m - 1ull) {
-                        const uint32_t j = (uint32_t)__builtin_ctzll(m);
-#pragma unroll
-                        for (int w = 0; w < NW; ++w) keep[side][w] |= s_fmask[side][j][w];
-                    }
-                }
-#pragma unroll
-                for (int w = 0; w < NW; ++w) todo[w] &= keep[0][w] & keep[1][w];
+        for (int w = 0; w < NW; ++w) {
+            for (uint32_t m = todo[w] & s_gmask[g0][w]; m; m &= m - 1u) {
+                const uint32_t t = 32u * w + (uint32_t)__builtin_ctz(m);
+                if (block_has(blk0, t, s_gkey[g0], s_t, sip, dip)) hits[w] |= 1u << (t & 31u);
             }
         }
     }
-    uint32_t steps = 0;
-    if constexpr (RANKED) {
-        // Without candidates (no model), one mask word: the tuples go in rank order
-        // (ascending best key), eight ranks per batch -- the filter bits of the batch's
-        // tuples this lane still needs, eight loads issued back to back, then this lane's
-        // probes of the passing ones. A tuple is needed while its best key beats the
-        // answer, so an answer found in an early batch drops the lane's later tuples
-        // before their filter loads (8.1 instead of 12.3 per header at 512k rules): the
-        // vector-memory data path is busy nearly all of the kernel's time. Batches no
-        // lane needs are skipped. (With candidates most lanes enter certification with
-        // an answer already, and this variant's 40 VGPRs cost more beside the predictor
-        // than its loads save.)
-        static_assert(NW == 1, "rank batches use one mask word");
-        for (uint32_t r0 = 0; r0 < ntup; r0 += 8) {
-            uint32_t want = 0;
+    {
+        uint32_t any = 0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const uint32_t r = r0 + q;
-                if (r < ntup && ((todo[0] >> s_order[r]) & 1u) &&
-                    kless(s_rank[r].x, s_rank[r].y, b.prio, b.id))
-                    want |= 1u << q;
-            }
-            if (!wave_or(want)) continue;
-            if (STATS) ++n_rounds;
-            uint32_t wd[8], pos[8];
+        for (int w = 0; w < NW; ++w) any |= todo[w];
+        if (wave_or(any)) {
+            for (uint32_t g = 0; g < ngroups; ++g) {
+                uint32_t m = 0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                wd[q] = 0;
-                pos[q] = 0;
-                if ((want >> q) & 1u) {
-                    const uint32_t t = s_order[r0 + q];
-                    const uint32_t bit =
-                        filter_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask) & filter_mask;
-                    wd[q] = filter[bit >> 5];
-                    pos[q] = bit & 31u;
-                    if (STATS) ++n_filter;
-                }
-            }
-            uint32_t pass = 0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) pass |= ((wd[q] >> pos[q]) & 1u) << q;
-            while (pass) {
-                const int q = __builtin_ctz(pass);
-                pass &= pass - 1u;
-                if (STATS) ++steps;
-                const uint32_t t = s_order[r0 + q];
-                if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) continue;
-                const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
-                search_tuple<STATS>(t, key_hash(t, ms, md), ms, md, sip, dip, sp, dp, proto,
-                                    slot_mask, slots, recs, b, n_probe, n_slots, n_recs);
+                for (int w = 0; w < NW; ++w) m |= todo[w] & s_gmask[g][w];
+                if (m && g != g0) gneed |= (GMask)1 << g;
             }
         }
-    } else {
-    // Phase 1: the filter bits of every remaining tuple, eight tuples per batch with their
-    // loads issued back to back; `hits` keeps the tuples whose bit is set. With one mask
-    // word a batch is eight consecutive tuples (batches no lane of the wave needs are
-    // skipped); with several, each lane takes its own next eight tuples, so the wave runs
-    // as many batches as its busiest lane needs rather than one per eight tuple indices.
-    uint32_t hits[NW];
-    if constexpr (NW > 1) {
-        uint32_t rem[NW];
+    }
+    for (;;) {
+        if (!wave_or(gneed != 0 ? 1u : 0u)) break;
+        if (STATS) ++n_rounds;
+        uint32_t gq[8];
+        uint2 blk[8];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            hits[w] = 0;
-            rem[w] = todo[w];
-        }
-        for (;;) {
-            uint32_t left = 0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) left |= rem[w];
-            if (!wave_or(left)) break;  // each batch takes up to eight tuples of every lane
-            if (STATS) ++n_rounds;
-            uint32_t tq[8], wd[8], pos[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                uint32_t t = kNoTuple;
-#pragma unroll
-                for (int w = 0; w < NW; ++w)
-                    if (t == kNoTuple && rem[w]) {
-                        t = 32u * w + (uint32_t)__builtin_ctz(rem[w]);
-                        rem[w] &= rem[w] - 1u;
-                    }
-                tq[q] = t;
-                wd[q] = 0;
-                pos[q] = 0;
-                if (t != kNoTuple) {
-                    const uint32_t bit =
-                        filter_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask) & filter_mask;
-                    wd[q] = filter[bit >> 5];
-                    pos[q] = bit & 31u;
-                    if (STATS) ++n_filter;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const uint32_t on = (wd[q] >> pos[q]) & 1u;
-#pragma unroll
-                for (int w = 0; w < NW; ++w)
-                    hits[w] |= ((tq[q] >> 5) == (uint32_t)w ? on : 0u) << (tq[q] & 31u);
+        for (int q = 0; q < 8; ++q) {
+            gq[q] = kNoGroup;
+            blk[q] = make_uint2(0u, 0u);
+            if (gneed) {
+                const uint32_t g = NW == 1 ? (uint32_t)__builtin_ctz((uint32_t)gneed)
+                                           : (uint32_t)__builtin_ctzll((unsigned long long)gneed);
+                gneed &= gneed - 1;
+                gq[q] = g;
+                blk[q] = load8(block_of(filter, s_gkey[g], sip, dip, filter_mask));
+                if (STATS) ++n_filter;
             }
         }
-    } else {
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            hits[w] = 0;
-            const uint32_t wave_todo = wave_or(todo[w]);
-            if (!wave_todo) continue;
-            for (uint32_t t0 = 0; t0 < 32u && 32u * w + t0 < ntup; t0 += 8) {
-                if (!((wave_todo >> t0) & 0xFFu)) continue;
-                if (STATS) ++n_rounds;
-                uint32_t wd[8], pos[8];
+        for (int q = 0; q < 8; ++q) {
+            if (gq[q] == kNoGroup) continue;
+            const uint32_t gk = s_gkey[gq[q]];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const uint32_t t = 32u * w + t0 + q;
-                    wd[q] = 0;
-                    pos[q] = 0;
-                    if ((todo[w] >> (t0 + q)) & 1u) {  // t < ntup: todo holds only existing tuples
-                        const uint32_t bit =
-                            filter_hash(t, sip & s_t[t].smask, dip & s_t[t].dmask) & filter_mask;
-                        wd[q] = filter[bit >> 5];
-                        pos[q] = bit & 31u;
-                        if (STATS) ++n_filter;
-                    }
+            for (int w = 0; w < NW; ++w) {
+                for (uint32_t m = todo[w] & s_gmask[gq[q]][w]; m; m &= m - 1u) {
+                    const uint32_t t = 32u * w + (uint32_t)__builtin_ctz(m);
+                    if (block_has(blk[q], t, gk, s_t, sip, dip)) hits[w] |= 1u << (t & 31u);
                 }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) hits[w] |= ((wd[q] >> pos[q]) & 1u) << (t0 + q);
             }
         }
     }
     // Phase 2: each lane searches its own passing tuples (so a wave takes as many steps as
-    // its busiest lane, not as the union of its lanes' tuples), skipping any whose best key
-    // can no longer beat the answer; the order does not matter for the result.
+    // its busiest lane, not as the union of its lanes' tuples) in tuple order -- tuples
+    // are numbered by first appearance in priority order, so good answers come early --
+    // skipping any whose best key can no longer beat the answer.
+    uint32_t steps = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         while (hits[w]) {
@@ -462,11 +367,9 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
             hits[w] &= hits[w] - 1u;
             if (STATS) ++steps;
             if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) continue;
-            const uint32_t ms = sip & s_t[t].smask, md = dip & s_t[t].dmask;
-            search_tuple<STATS>(t, key_hash(t, ms, md), ms, md, sip, dip, sp, dp, proto, slot_mask,
-                                slots, recs, b, n_probe, n_slots, n_recs);
+            search_tuple<STATS>(t, s_t, sip, dip, sp, dp, proto, slot_mask, slots, recs, b, n_probe,
+                                n_slots, n_recs);
         }
-    }
     }
     if (STATS) n_steps = wave_max(steps);
     if (active) {
@@ -509,17 +412,15 @@ hipError_t launch_classify(const tang_ruleset_t* rs, const tang_header_t* d_hdr,
         const uint4* h = reinterpret_cast<const uint4*>(d_hdr) + base;
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, grid, block, 0, s, h, d_out + base, m, rs->d_slots, rs->d_recs,
-                               rs->d_cmask, rs->d_filter, rs->d_tt, kcand, rs->d_stats);
+                               rs->d_cmask, reinterpret_cast<const uint2*>(rs->d_filter), rs->d_tt,
+                               kcand, rs->d_stats);
         };
-        if (rs->nw == 1 && kcand == 0) {
-            if (stats) go(k_classify<true, 1, true>);
-            else go(k_classify<false, 1, true>);
-        } else if (rs->nw == 1) {
-            if (stats) go(k_classify<true, 1, false>);
-            else go(k_classify<false, 1, false>);
+        if (rs->nw == 1) {
+            if (stats) go(k_classify<true, 1>);
+            else go(k_classify<false, 1>);
         } else {
-            if (stats) go(k_classify<true, kMaskWords, false>);
-            else go(k_classify<false, kMaskWords, false>);
+            if (stats) go(k_classify<true, kMaskWords>);
+            else go(k_classify<false, kMaskWords>);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -49,29 +49,35 @@ constexpr uint32_t kKindShift = 8;   // tuples < 256; tuple | kind << 8 fits the
 // kMaskWords words per rule (a side array indexed like the records) up to 256 tuples.
 constexpr int kMaskWords = 8;
 
-// Rec (32 B): one rule as the bucket scan reads it. Two 16-byte loads.
-//   sip, dip : prefix values, bits beyond the length zeroed
+// Rec (32 B): one rule as the bucket scan reads it, hot half first. The scan reads the
+// first 16 bytes of each record (one load): ports, priority and the protocol/length
+// word decide a match for a rule held by its own tuple. The second half is read only
+// for a match (its id and conflict mask), a priority tie (the id breaks it), or a rule
+// held by a coarser tuple than its own signature (its prefixes must be checked).
 //   sp, dp   : lo | hi << 16 (inclusive)
-//   meta     : sip_len (bits 0-5) | dip_len (6-11) | proto (12-19) | exact-proto (20)
-//              | tuple (21-31)
+//   prio     : priority; (prio, id) is the key, kDead in both marks a vacated record
+//   meta     : proto (bits 0-7) | exact-proto (8) | prefix check (9) | sip_len (10-15)
+//              | dip_len (16-21) | tuple (22-31)
+//   sip, dip : prefix values, bits beyond the length zeroed
+//   id       : rule id
 //   cmask    : conflict tuples of a ruleset of at most 32 tuples (wider ones: side
 //              array) -- tuples that hold a higher-priority rule whose box meets this
 //              rule's box (a superset after deletes)
-//   prio, id : the (priority, id) key; kDead marks a vacated record
 struct alignas(16) Rec {
-    uint32_t sip, dip, sp, dp, meta, cmask, prio, id;
+    uint32_t sp, dp, prio, meta, sip, dip, id, cmask;
 };
 constexpr uint32_t kDead = 0xFFFFFFFFu;
 
 __host__ __device__ inline uint32_t meta_pack(uint32_t sl, uint32_t dl, uint32_t proto,
-                                              uint32_t exact, uint32_t tuple) {
-    return sl | (dl << 6) | (proto << 12) | (exact << 20) | (tuple << 21);
+                                              uint32_t exact, uint32_t tuple, uint32_t check) {
+    return proto | (exact << 8) | (check << 9) | (sl << 10) | (dl << 16) | (tuple << 22);
 }
-__host__ __device__ inline uint32_t meta_sl(uint32_t m) { return m & 63u; }
-__host__ __device__ inline uint32_t meta_dl(uint32_t m) { return (m >> 6) & 63u; }
-__host__ __device__ inline uint32_t meta_proto(uint32_t m) { return (m >> 12) & 255u; }
-__host__ __device__ inline uint32_t meta_exact(uint32_t m) { return (m >> 20) & 1u; }
-__host__ __device__ inline uint32_t meta_tuple(uint32_t m) { return (m >> 21) & 2047u; }
+__host__ __device__ inline uint32_t meta_proto(uint32_t m) { return m & 255u; }
+__host__ __device__ inline uint32_t meta_exact(uint32_t m) { return (m >> 8) & 1u; }
+__host__ __device__ inline uint32_t meta_check(uint32_t m) { return (m >> 9) & 1u; }
+__host__ __device__ inline uint32_t meta_sl(uint32_t m) { return (m >> 10) & 63u; }
+__host__ __device__ inline uint32_t meta_dl(uint32_t m) { return (m >> 16) & 63u; }
+__host__ __device__ inline uint32_t meta_tuple(uint32_t m) { return m >> 22; }
 
 // Prefix mask of length l (0..32): the top l bits; l = 0 gives 0 (no shift by 32).
 __host__ __device__ inline uint32_t pmask(uint32_t l) {
@@ -83,6 +89,11 @@ __host__ __device__ inline uint32_t pmask(uint32_t l) {
 struct TupleDev {
     uint32_t smask, dmask, best_prio, best_id;
 };
+// Filter groups: the tuples whose longer prefix is the SIP (sip_len >= dip_len) share a
+// group per SIP length, the others a group per DIP length; tuple (0, 0), whose only
+// possible key always has a bucket, has none. At most 64 groups (32 lengths per field).
+constexpr int kMaxGroups = 64;
+constexpr uint32_t kNoGroup = 0xFFu;
 struct TupleTable {
     TupleDev t[TANG_MAX_TUPLES];
     uint8_t order[TANG_MAX_TUPLES];  // tuple indices by ascending best key
@@ -92,20 +103,20 @@ struct TupleTable {
     uint32_t n;                       // number of tuples
     uint32_t all_mask[kMaskWords];    // bits of all tuples
     uint32_t slot_mask;               // slots - 1
-    uint32_t filter_mask;             // filter bits - 1
+    uint32_t filter_mask;             // filter blocks - 1
     uint32_t nw;                      // mask words of this ruleset (1 or kMaskWords)
-    // Field pre-check of wide tuple spaces: per field (0 = SIP, 1 = DIP) the distinct prefix
-    // lengths of the tuples, and per length the mask of the tuples that have it.
-    uint8_t flen[2][33];
-    uint32_t nflen[2];
-    uint32_t fmask[2][33][kMaskWords];
+    uint8_t gid[TANG_MAX_TUPLES];     // filter group of each tuple (kNoGroup: none)
+    uint32_t ngroups;
+    uint32_t gkey[kMaxGroups];        // side (bit 6: 1 = DIP) | prefix length (bits 0-5)
+    uint32_t gmask[kMaxGroups][kMaskWords];  // tuples of each group
+    uint32_t nogroup[kMaskWords];     // tuples without a group (always pass)
 };
 
 // Key hash: two chained MurmurHash3 32-bit finalisers (fmix32, Appleby, public domain),
 // first over the masked SIP salted by the tuple index, then over that result xor the
 // masked DIP. Each stage is a bijection, so structured keys (prefixes whose only varying
 // bits are the top byte) do not collapse. The low half of the result picks the slot.
-// The bucket filter uses its own cheaper hash (filter_hash below).
+// The bucket filter uses its own cheaper hashes (filter_block / filter_bit below).
 __host__ __device__ inline uint32_t fmix32(uint32_t h) {
     h ^= h >> 16;
     h *= 0x85EBCA6Bu;
@@ -121,32 +132,27 @@ __host__ __device__ inline uint64_t key_hash(uint32_t t, uint32_t ms, uint32_t m
     return ((uint64_t)f << 32) | h;
 }
 __host__ __device__ inline uint32_t slot_of(uint64_t h) { return (uint32_t)h; }
-// Filter bit of a key: the masked SIP xor the masked DIP rotated by 13 (so the /8 and /16
-// prefixes of the two fields land on different bits) xor a tuple salt, then two
-// multiply-xorshift rounds. Only placement of filter bits depends on it (a collision can
-// only set a bit that a lookup then checks in vain), and it costs a third of key_hash.
-__host__ __device__ inline uint32_t filter_hash(uint32_t t, uint32_t ms, uint32_t md) {
-    uint32_t x = ms ^ ((md << 13) | (md >> 19)) ^ ((t + 1u) * 0x9E3779B9u);
+// Bucket filter, blocked by prefix group. A main bucket (t, ms, md) of a tuple with
+// lengths (ls, ld) belongs to the tuple's filter group: the SIP group of length ls when
+// ls >= ld, else the DIP group of length ld. The group value v (ms or md) picks one
+// 64-bit block, filter_block(gkey, v); the other masked field o (md or ms) and the tuple
+// pick the bit, filter_bit(t, o). A header then reads one block per group for all the
+// tuples of that group (at most 5 blocks for the 25 tuples of five lengths per field),
+// where a bit per tuple took one load each. A clear bit means no bucket; a set bit may
+// be a collision, which only costs a slot walk. Placement never affects answers.
+__host__ __device__ inline uint32_t filter_block(uint32_t gkey, uint32_t v) {
+    uint32_t x = v ^ ((gkey + 1u) * 0x9E3779B9u);
     x *= 0x85EBCA6Bu;
     x ^= x >> 15;
     x *= 0xC2B2AE35u;
     x ^= x >> 16;
     return x;
 }
-
-// Bucket filter: one bit per filter_hash(key) over all buckets ever created (a superset
-// after deletes). A header's masked key whose bit is clear has no bucket in that tuple,
-// so the slot walk is skipped; at >= 32 bits per bucket about 3% of absent keys pass.
-// Sized to stay L2-resident (2 MB at 512k rules).
-//
-// Wide tuple spaces (more than 32 tuples) also put each bucket's two field keys in the
-// filter -- (SIP length, masked SIP) and (DIP length, masked DIP), under salts that no
-// tuple index reaches -- at 64 bits per bucket. A tuple can hold a bucket for a header
-// only if both of the header's field keys for the tuple's lengths are present, so a
-// header first checks one bit per distinct length of each field instead of one per tuple.
-constexpr uint32_t kFieldSalt = 1024;
-__host__ __device__ inline uint32_t field_filter_hash(uint32_t side, uint32_t len, uint32_t v) {
-    return side == 0 ? filter_hash(kFieldSalt + len, v, 0u) : filter_hash(kFieldSalt + 64u + len, 0u, v);
+__host__ __device__ inline uint32_t filter_bit(uint32_t t, uint32_t o) {
+    return ((o ^ ((t + 1u) * 0x7FEB352Du)) * 0x846CA68Bu) >> 26;
+}
+__host__ __device__ inline uint32_t group_key_of(uint32_t ls, uint32_t ld) {
+    return ls >= ld ? ls : (64u | ld);
 }
 
 // Device-side counters for tang_stats_t (kStatCopies copies, summed on the host).
@@ -236,7 +242,7 @@ struct tang_ruleset_s {
     std::vector<Bucket> buckets;
     std::unordered_map<BKey, uint32_t, BKeyHash> bucket_of;
     std::vector<tang::Slot> slots;                 // host mirror of the slot table
-    std::vector<uint32_t> filter;                  // host mirror of the bucket filter
+    std::vector<uint32_t> filter;                  // host mirror of the bucket filter (2 words per block)
     uint32_t rec_used = 0, rec_cap = 0;
     uint32_t nw = 1;   // conflict-mask words per rule (fixed at build: 1, or kMaskWords)
 

@@ -75,28 +75,24 @@ std::vector<uint32_t> split_bucket(tang_ruleset_t* rs, uint32_t b) {
     return touched;
 }
 
-void filter_bit(std::vector<uint32_t>& f, uint32_t h) {
-    const uint32_t b = h & ((uint32_t)f.size() * 32u - 1u);
-    f[b >> 5] |= 1u << (b & 31u);
-}
-
-// The filter bits of a main bucket: its key, and in a wide tuple space its field keys.
+// The filter bit of a main bucket: in the block its group value picks (tuple (0, 0)
+// has no group: its one possible key always has a bucket).
 void filter_add(tang_ruleset_t* rs, const tang_ruleset_t::Bucket& bk) {
-    filter_bit(rs->filter, filter_hash(bk.t, bk.ms, bk.md));
-    if (rs->nw > 1) {
-        filter_bit(rs->filter, field_filter_hash(0, rs->sigs[bk.t].first, bk.ms));
-        filter_bit(rs->filter, field_filter_hash(1, rs->sigs[bk.t].second, bk.md));
-    }
+    const uint32_t ls = rs->sigs[bk.t].first, ld = rs->sigs[bk.t].second;
+    if (ls == 0 && ld == 0) return;
+    const uint32_t gk = group_key_of(ls, ld);
+    const uint32_t v = gk & 64u ? bk.md : bk.ms, o = gk & 64u ? bk.ms : bk.md;
+    const uint32_t blocks = (uint32_t)rs->filter.size() / 2;
+    const uint32_t blk = filter_block(gk, v) & (blocks - 1u), bit = filter_bit(bk.t, o);
+    rs->filter[2 * blk + (bit >> 5)] |= 1u << (bit & 31u);
 }
-
-uint64_t filter_bits_per_bucket(const tang_ruleset_t* rs) { return rs->nw > 1 ? 64 : 32; }
 
 // Slot table at load <= 1/4 (short walks) and the bucket filter at >= 32 bits per bucket
-// (64 with field keys).
+// (blocks of 64 bits).
 void rebuild_slots(tang_ruleset_t* rs) {
     const uint64_t nb = rs->buckets.size();
     rs->slots.assign(next_pow2(std::max<uint64_t>(1024, 4 * nb + 4)), Slot{0, 0, kEmptyTL, 0});
-    rs->filter.assign(std::max<uint64_t>(2048, next_pow2(filter_bits_per_bucket(rs) * (nb + 1)) / 32), 0u);
+    rs->filter.assign(2 * (uint64_t)next_pow2(std::max<uint64_t>(1024, (nb + 1) / 2)), 0u);
     for (uint32_t b = 0; b < rs->buckets.size(); ++b) {
         auto& bk = rs->buckets[b];
         bk.slot = slot_insert(rs->slots, slot_value(rs, b));
@@ -146,7 +142,11 @@ Rec make_rec(const tang_ruleset_t* rs, uint32_t h) {
     x.dip = r.dip;
     x.sp = (uint32_t)r.sp_lo | ((uint32_t)r.sp_hi << 16);
     x.dp = (uint32_t)r.dp_lo | ((uint32_t)r.dp_hi << 16);
-    x.meta = meta_pack(r.sip_len, r.dip_len, r.proto, r.proto_mask ? 1u : 0u, hr.tuple);
+    // a rule held by a coarser tuple than its own signature (restricted insertion) has
+    // its prefixes checked in the scan; in its own tuple the bucket key implies them
+    const auto& sig = rs->sigs[hr.tuple];
+    const uint32_t check = (sig.first != r.sip_len || sig.second != r.dip_len) ? 1u : 0u;
+    x.meta = meta_pack(r.sip_len, r.dip_len, r.proto, r.proto_mask ? 1u : 0u, hr.tuple, check);
     x.cmask = 0;
     x.prio = r.priority;
     x.id = r.id;
@@ -185,17 +185,23 @@ TupleTable make_tuple_table(const tang_ruleset_t* rs) {
     tt.n = n;
     for (uint32_t t = 0; t < n; ++t) tt.all_mask[t >> 5] |= 1u << (t & 31u);
     tt.nw = rs->nw;
+    // filter groups in order of first appearance over the tuples
     for (uint32_t t = 0; t < n; ++t) {
-        const uint8_t lens[2] = {rs->sigs[t].first, rs->sigs[t].second};
-        for (int side = 0; side < 2; ++side) {
-            uint32_t j = 0;
-            while (j < tt.nflen[side] && tt.flen[side][j] != lens[side]) ++j;
-            if (j == tt.nflen[side]) tt.flen[side][tt.nflen[side]++] = lens[side];
-            tt.fmask[side][j][t >> 5] |= 1u << (t & 31u);
+        const uint32_t ls = rs->sigs[t].first, ld = rs->sigs[t].second;
+        if (ls == 0 && ld == 0) {
+            tt.gid[t] = (uint8_t)kNoGroup;
+            tt.nogroup[t >> 5] |= 1u << (t & 31u);
+            continue;
         }
+        const uint32_t gk = group_key_of(ls, ld);
+        uint32_t g = 0;
+        while (g < tt.ngroups && tt.gkey[g] != gk) ++g;
+        if (g == tt.ngroups) tt.gkey[tt.ngroups++] = gk;
+        tt.gid[t] = (uint8_t)g;
+        tt.gmask[g][t >> 5] |= 1u << (t & 31u);
     }
     tt.slot_mask = rs->slots.empty() ? 0 : (uint32_t)rs->slots.size() - 1;
-    tt.filter_mask = rs->filter.empty() ? 0 : (uint32_t)rs->filter.size() * 32u - 1u;
+    tt.filter_mask = rs->filter.empty() ? 0 : (uint32_t)rs->filter.size() / 2u - 1u;
     return tt;
 }
 
@@ -606,7 +612,7 @@ int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
     if (rs->buckets.size() != nb_before) {
         // keep the slot table at most 1/3 full and the filter at >= half its bits per bucket
         if (3 * rs->buckets.size() + 3 > rs->slots.size() ||
-            filter_bits_per_bucket(rs) / 2 * rs->buckets.size() > rs->filter.size() * 32) {
+            16 * rs->buckets.size() > rs->filter.size() * 32) {
             rebuild_slots(rs);
             rehash = true;
         } else {
