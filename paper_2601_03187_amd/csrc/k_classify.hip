@@ -67,8 +67,9 @@ __device__ __forceinline__ void scan_list(uint32_t t, uint32_t off, uint32_t len
         const uint4 h = load16(p);  // sp, dp, prio, meta
         if (STATS) ++n_recs;
         if (h.z > b.prio) break;
-        bool ok = (sp >= (h.x & 0xFFFFu)) & (sp <= (h.x >> 16)) & (dp >= (h.y & 0xFFFFu)) &
-                  (dp <= (h.y >> 16)) & ((meta_exact(h.w) == 0) | (proto == meta_proto(h.w)));
+        const bool ok = ((uint32_t)(sp >= (h.x & 0xFFFFu)) & (uint32_t)(sp <= (h.x >> 16)) &
+                         (uint32_t)(dp >= (h.y & 0xFFFFu)) & (uint32_t)(dp <= (h.y >> 16)) &
+                         ((uint32_t)(meta_exact(h.w) == 0) | (uint32_t)(proto == meta_proto(h.w)))) != 0u;
         if (!ok && h.z < b.prio) continue;
         const uint4 c = load16(p + 1);  // sip, dip, id, cmask
         if (h.z == b.prio && !(c.z < b.id)) break;
@@ -355,20 +356,138 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
             }
         }
     }
-    // Phase 2: each lane searches its own passing tuples (so a wave takes as many steps as
-    // its busiest lane, not as the union of its lanes' tuples) in tuple order -- tuples
-    // are numbered by first appearance in priority order, so good answers come early --
-    // skipping any whose best key can no longer beat the answer.
+    // Phase 2: each lane searches its own passing tuples in tuple order -- tuples are
+    // numbered by first appearance in priority order, so good answers come early --
+    // skipping any whose best key can no longer beat the answer. The probes run as one
+    // flat loop of loads per lane (slot, record first half, record second half; a lane
+    // between probes takes its next tuple at the top of the loop), so a wave takes as
+    // many iterations as its busiest lane issues loads in total. Probe by probe in
+    // lockstep, a wave would wait at every probe for its lane with the longest walk or
+    // bucket scan, and lanes with long scans rarely coincide.
     uint32_t steps = 0;
+    {
+        enum : uint32_t { P_NEXT = 0, P_SLOT, P_HOT, P_COLD, P_DONE };
+        constexpr uint32_t kMain = 8;   // `sub` while walking to a tuple's main bucket
+        uint32_t ps = active ? P_NEXT : P_DONE;
+        uint32_t ct = 0, tk = 0, k0 = 0, k1 = 0, walk = 0, sub = kMain, bi = 0, left = 0;
+        uint32_t hp = 0, hm = 0, hok = 0;
+        const uint4* ld = reinterpret_cast<const uint4*>(slots);
+        for (;;) {
+            if (ps == P_NEXT) {
+                ps = P_DONE;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        while (hits[w]) {
-            const uint32_t t = 32u * w + (uint32_t)__builtin_ctz(hits[w]);
-            hits[w] &= hits[w] - 1u;
-            if (STATS) ++steps;
-            if (!kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) continue;
-            search_tuple<STATS>(t, s_t, sip, dip, sp, dp, proto, slot_mask, slots, recs, b, n_probe,
-                                n_slots, n_recs);
+                for (int w = 0; w < NW; ++w) {
+                    while (hits[w]) {
+                        const uint32_t t = 32u * w + (uint32_t)__builtin_ctz(hits[w]);
+                        hits[w] &= hits[w] - 1u;
+                        if (kless(s_t[t].best_prio, s_t[t].best_id, b.prio, b.id)) {
+                            ct = t;
+                            ps = P_SLOT;
+                            break;
+                        }
+                    }
+                    if (ps == P_SLOT) break;
+                }
+                if (ps == P_SLOT) {
+                    if (STATS) ++n_probe;
+                    tk = ct;
+                    k0 = sip & s_t[ct].smask;
+                    k1 = dip & s_t[ct].dmask;
+                    sub = kMain;
+                    walk = 0;
+                    ld = reinterpret_cast<const uint4*>(slots + (slot_of(key_hash(tk, k0, k1)) & slot_mask));
+                }
+            }
+            if (!__ballot(ps != P_DONE)) break;
+            if (STATS && ps != P_DONE) ++steps;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (ps != P_DONE) v = load16(ld);
+            bool list_done = false;
+            if (ps == P_SLOT) {
+                if (STATS) ++n_slots;
+                if (v.z == kEmptyTL) {
+                    list_done = true;
+                } else if (v.x == k0 && v.y == k1 && (v.z >> kTlShift) == tk) {
+                    if (sub == kMain && (v.w & kSplit)) {
+                        bi = v.w & ~kSplit;   // a split bucket: the sub-lists the header selects
+                        sub = 0;
+                        list_done = true;
+                    } else if ((v.z & kMaxBucketLen) == 0) {
+                        list_done = true;
+                    } else {
+                        left = (v.z & kMaxBucketLen) - 1u;
+                        ps = P_HOT;
+                        ld = reinterpret_cast<const uint4*>(recs + v.w);
+                    }
+                } else if (++walk > slot_mask) {
+                    list_done = true;   // only a corrupted table has no empty slot
+                } else {
+                    const uint32_t h = (uint32_t)(reinterpret_cast<const Slot*>(ld) - slots);
+                    ld = reinterpret_cast<const uint4*>(slots + ((h + 1u) & slot_mask));
+                }
+            } else if (ps == P_HOT) {
+                if (STATS) ++n_recs;
+                if (v.z > b.prio) {
+                    list_done = true;   // this and every later record cannot beat the answer
+                } else {
+                    const bool ok = ((uint32_t)(sp >= (v.x & 0xFFFFu)) & (uint32_t)(sp <= (v.x >> 16)) &
+                                     (uint32_t)(dp >= (v.y & 0xFFFFu)) & (uint32_t)(dp <= (v.y >> 16)) &
+                                     ((uint32_t)(meta_exact(v.w) == 0) |
+                                      (uint32_t)(proto == meta_proto(v.w)))) != 0u;
+                    if (!ok && v.z < b.prio) {
+                        if (left) {
+                            --left;
+                            ld += 2;
+                        } else {
+                            list_done = true;
+                        }
+                    } else {
+                        hp = v.z;
+                        hm = v.w;
+                        hok = ok ? 1u : 0u;
+                        ps = P_COLD;
+                        ld += 1;
+                    }
+                }
+            } else if (ps == P_COLD) {
+                bool next = false;
+                if (hp == b.prio && !(v.z < b.id)) {
+                    list_done = true;
+                } else if (!hok) {
+                    next = true;
+                } else if (meta_check(hm) && ((((sip ^ v.x) & pmask(meta_sl(hm))) |
+                                               ((dip ^ v.y) & pmask(meta_dl(hm)))) != 0u)) {
+                    next = true;
+                } else {
+                    b = Best{hp, v.z, v.w, ct, (uint32_t)(reinterpret_cast<const Rec*>(ld - 1) - recs)};
+                    list_done = true;
+                }
+                if (next) {
+                    if (left) {
+                        --left;
+                        ps = P_HOT;
+                        ld += 1;
+                    } else {
+                        list_done = true;
+                    }
+                }
+            }
+            if (list_done) {
+                if (sub < 4u) {
+                    // the next sub-list of a split bucket
+                    const uint32_t kind = sub == 0 ? kSubDp : sub == 1 ? kSubSp : sub == 2 ? kSubProto : kSubRest;
+                    const uint32_t val = sub == 0 ? dp : sub == 1 ? sp : sub == 2 ? proto : 0u;
+                    ++sub;
+                    tk = ct | (kind << kKindShift);
+                    k0 = bi;
+                    k1 = val;
+                    walk = 0;
+                    ps = P_SLOT;
+                    ld = reinterpret_cast<const uint4*>(slots + (slot_of(key_hash(tk, k0, k1)) & slot_mask));
+                } else {
+                    ps = P_NEXT;
+                }
+            }
         }
     }
     if (STATS) n_steps = wave_max(steps);
