@@ -141,8 +141,8 @@ __device__ __forceinline__ const uint2* block_of(const uint2* __restrict__ filte
 __device__ __forceinline__ bool block_has(uint2 blk, uint32_t t, uint32_t gk, const TupleDev* s_t,
                                           uint32_t sip, uint32_t dip) {
     const uint32_t o = gk & 64u ? (sip & s_t[t].smask) : (dip & s_t[t].dmask);
-    const uint32_t bit = filter_bit(t, o);
-    return ((bit & 32u ? blk.y : blk.x) >> (bit & 31u)) & 1u;
+    const uint32_t bits = filter_bits(t, o), b1 = bits & 63u, b2 = bits >> 8;
+    return ((b1 & 32u ? blk.y : blk.x) >> (b1 & 31u)) & ((b2 & 32u ? blk.y : blk.x) >> (b2 & 31u)) & 1u;
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {

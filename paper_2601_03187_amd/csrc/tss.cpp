@@ -83,8 +83,8 @@ void filter_add(tang_ruleset_t* rs, const tang_ruleset_t::Bucket& bk) {
     const uint32_t gk = group_key_of(ls, ld);
     const uint32_t v = gk & 64u ? bk.md : bk.ms, o = gk & 64u ? bk.ms : bk.md;
     const uint32_t blocks = (uint32_t)rs->filter.size() / 2;
-    const uint32_t blk = filter_block(gk, v) & (blocks - 1u), bit = filter_bit(bk.t, o);
-    rs->filter[2 * blk + (bit >> 5)] |= 1u << (bit & 31u);
+    const uint32_t blk = filter_block(gk, v) & (blocks - 1u), bits = filter_bits(bk.t, o);
+    for (uint32_t bit : {bits & 63u, bits >> 8}) rs->filter[2 * blk + (bit >> 5)] |= 1u << (bit & 31u);
 }
 
 // Slot table at load <= 1/4 (short walks) and the bucket filter at >= 32 bits per bucket
