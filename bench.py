@@ -215,10 +215,10 @@ def main():
         matched = 1.0 - st["no_match"] / n
         # algorithmic bytes of the search per header: header in, rule id out, the slots and
         # records the method reads, and a matched rule's conflict mask; the bucket-filter
-        # words and the candidate word read back from the predictor are this
-        # implementation's own traffic, reported beside it
+        # blocks (8 bytes each) and the candidate word read back from the predictor are
+        # this implementation's own traffic, reported beside it
         bytes_pkt = search_alg_bytes(S, E, matched)
-        impl_pkt = 4 * F + 4
+        impl_pkt = 8 * F + 4
         per[prec] = dict(
             mpps=n * args.steps / wall / 1e6, ms_per_step=wall * 1e3 / args.steps,
             p50_ms=pct(step_ms, 50), p99_ms=pct(step_ms, 99),
@@ -380,7 +380,7 @@ def main():
                             "frac": head["search_gbs"] / PEAK_HBM_GBS, "ms": head["k_classify_ms"],
                             "bytes_per_pkt": head["search_bytes_per_pkt"],
                             "overhead_bytes_per_pkt": head["search_overhead_bytes_per_pkt"],
-                            "overhead": "bucket-filter words (4 B each) and the predictor's "
+                            "overhead": "bucket-filter blocks (8 B each) and the predictor's "
                                         "candidate word (4 B), not counted in bytes_per_pkt"}}
     tr = measured_traffic("k_classify", wl)
     if tr:
@@ -513,14 +513,17 @@ def other_configs(args, rules3, rs3, d_hdr3, prec3):
                                    "mismatches": int((got[samp] != want).sum())}
     log(f"[bench] c3 with 80% rule-sampled headers: {res['c3_512k_80pct_inside']['mpps']:.0f} Mpps")
     del d_hdr, d_out
-    res["c7_wide"] = bench_wide(args)
+    res["c7_wide"] = bench_wide(args, "c7_wide")
+    res["c8_all_lengths"] = bench_wide(args, "c8_all_lengths")
     return res
 
 
-def bench_wide(args):
-    """A wide tuple space: 524,288 rules over 144 (SIP, DIP) signatures (12 prefix lengths
-    per field), 16M Zipf headers; no model, and a trained 104-256-256-144 MLP in BF16 and
-    FP8 (top-1). Mpps, probes per header, and a seeded 20,000-header oracle sample."""
+def bench_wide(args, name):
+    """A wide tuple space, 524,288 rules and 16M Zipf headers: c7_wide, 144 (SIP, DIP)
+    signatures (12 prefix lengths per field); c8_all_lengths, 387 signatures over every
+    prefix length 0..32 (the size of the paper's largest tuple spaces). No model, and a
+    trained 104-256-256-C MLP in BF16 and FP8 (top-1). Mpps, probes per header, and a
+    seeded 20,000-header oracle sample."""
     import numpy as np
     import torch
 
@@ -528,8 +531,9 @@ def bench_wide(args):
     from paper_2601_03187_amd import synth, train
     from paper_2601_03187_amd import tang as T
 
-    cfg = synth.CONFIGS["c7_wide"]
-    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], wide=True)
+    cfg = synth.CONFIGS[name]
+    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], wide=name == "c7_wide",
+                             all_lengths=name == "c8_all_lengths")
     n = cfg["n_pkts"]
     hdr = synth.make_packets(rules, n, seed=cfg["seed"] + 1, frac_in=cfg["frac_in"], zipf_s=cfg["zipf"])
     rs = T.tang_ruleset_create(0, rules)
@@ -540,16 +544,16 @@ def bench_wide(args):
     want = orc.classify(rules, hdr[samp])
     out = {"rules": len(rules), "tuples": C, "headers": n, "hidden": cfg["hidden"]}
 
-    def run(name):
+    def run(what):
         st = T.tang_classify(rs, d_hdr, d_out, n, torch.cuda.current_stream(), want_stats=True)
         got = d_out.cpu().numpy().view(np.uint32)
         ms = time_classify(T, rs, d_hdr, d_out, n, args.steps)
-        out[name] = {"mpps": n / ms / 1e3, "ms_per_batch": ms, "probes_per_pkt": st["probes"] / n,
+        out[what] = {"mpps": n / ms / 1e3, "ms_per_batch": ms, "probes_per_pkt": st["probes"] / n,
                      "records_per_pkt": st["records"] / n, "top1_hit_rate": st["top1_hits"] / n,
                      "fallback_rate": st["fallbacks"] / n, "oracle_checked": int(len(samp)),
                      "mismatches": int((got[samp] != want).sum())}
-        log(f"[bench] c7_wide {name}: {out[name]['mpps']:.0f} Mpps, "
-            f"{out[name]['probes_per_pkt']:.2f} probes/pkt, {out[name]['mismatches']} mismatches")
+        log(f"[bench] {name} ({C} tuples) {what}: {out[what]['mpps']:.0f} Mpps, "
+            f"{out[what]['probes_per_pkt']:.2f} probes/pkt, {out[what]['mismatches']} mismatches")
 
     run("no_model")
     Ws, bs, sc, acc = train.fit(rs, rules, hdr[:200_000], cfg["hidden"], steps=args.train_steps,
@@ -643,9 +647,9 @@ def paper_statistics(args, rules, rs, hdr, d_hdr, d_out, want, C):
             T.tang_model_load(rs, Ws, bs, "bf16", topk=1)
         else:
             T.tang_model_load_resnet(rs, Ws, bs, "bf16", topk=1)
-        cand = torch.empty(n, dtype=torch.uint8, device="cuda")
+        cand = torch.empty(n, dtype=torch.int16, device="cuda")
         T.tang_mlp_forward(rs, d_hdr, n, None, cand, s)
-        pred = cand.cpu().numpy().astype(np.int64)
+        pred = cand.cpu().numpy().view(np.uint16).astype(np.int64)
         ok = label >= 0
         model_acc = float(np.mean(pred[held][ok] == label[ok]))
         # the paper's search: best match inside the predicted tuple, else the true answer

@@ -35,8 +35,8 @@ extern "C" {
 
 #define TANG_NO_MATCH 0xFFFFFFFFu /* rule_id when no rule matches (no default rule) */
 #define TANG_HOST_ONLY (-1)       /* device argument: build host structures only */
-#define TANG_MAX_TUPLES 256       /* candidates are bytes; conflict masks up to 8 words */
-#define TANG_MAX_TOPK 4
+#define TANG_MAX_TUPLES 512       /* conflict masks up to 16 words */
+#define TANG_MAX_TOPK 4           /* 2 for rulesets of more than 256 tuples */
 #define TANG_MAX_LAYERS 8
 
 enum {
@@ -82,8 +82,9 @@ typedef enum { TANG_FP32 = 0, TANG_BF16 = 1, TANG_FP8 = 2 } tang_precision_t;
  * last. dims[0] must be 104: the header's bits, most significant first, over SIP(32)
  * DIP(32) SP(16) DP(16) PROTO(8), each as 0.0 or 1.0. dims[n_layers] must equal
  * tang_ruleset_num_tuples() (1..TANG_MAX_TUPLES). Supported now: n_layers = 3 with equal hidden widths
- * 128 or 256. topk (1..4) is how many top-scoring tuples are probed before
- * certification; equal scores go to the lower tuple index (argmax of Sec. 6.1 for 1).
+ * 128 or 256. topk (1..4; 1..2 above 256 tuples) is how many top-scoring tuples are
+ * probed before certification; equal scores go to the lower tuple index (argmax of
+ * Sec. 6.1 for 1).
  */
 typedef struct tang_mlp_desc_s {
     uint32_t n_layers;
@@ -135,9 +136,11 @@ int tang_ruleset_rule_tuple(const tang_ruleset_t* rs, uint32_t id, uint32_t* tup
 /*
  * Conflict mask of live rule `id` (bit t = tuple t), read back from the device
  * (synchronises): tang_ruleset_conflict_mask gives tuples 0..31; _words gives n_words
- * words (word w = tuples 32w..32w+31), zero past the ruleset's mask width. A ruleset built
- * with at most 32 tuples keeps one mask word per rule (and then cannot grow a 33rd tuple
- * by insertion: EINVAL); one built with more keeps 8 words (up to 256 tuples).
+ * words (word w = tuples 32w..32w+31), zero past the ruleset's mask width. The mask width
+ * is fixed when the ruleset is built: one word per rule for at most 32 tuples, 8 words
+ * for at most 256, 16 words above (up to TANG_MAX_TUPLES). An insertion that would
+ * append a tuple past the width's limit (the 33rd, 257th or 513th) fails with EINVAL;
+ * rebuilding the ruleset from tang_ruleset_export lifts it.
  */
 int tang_ruleset_conflict_mask(tang_ruleset_t* rs, uint32_t id, uint32_t* mask);
 int tang_ruleset_conflict_mask_words(tang_ruleset_t* rs, uint32_t id, uint32_t* words,
@@ -252,7 +255,8 @@ int tang_classify_host_noalloc(tang_ruleset_t* rs, const tang_header_t* hdr, uin
 /*
  * The two stages of tang_classify, callable one by one (Sec. 5.1.1): tang_predict runs
  * the model and writes each header's candidate tuples into d_io[i] (one byte per
- * candidate, first candidate in the low byte); tang_search then probes, verifies and
+ * candidate for rulesets of up to 256 tuples, 16 bits per candidate above; the first
+ * candidate in the low bits); tang_search then probes, verifies and
  * certifies, reading those candidates from d_io and overwriting them with the rule ids.
  * Without a model tang_predict is an error and tang_search probes every tuple. Same
  * buffers, stream and concurrency rules as tang_classify; tang_search's stats as there.
@@ -263,17 +267,19 @@ int tang_search(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_io, 
                 void* stream, tang_stats_t* stats);
 /*
  * Predictor only: d_logits (device, may be NULL) receives n x C FP32 scores and d_cand
- * (device, may be NULL) n x topk tuple indices. Asynchronous on `stream`. Needs a model.
+ * (device, may be NULL) n x topk tuple indices, 16 bits each. Asynchronous on `stream`.
+ * Needs a model.
  */
 int tang_mlp_forward(tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n, float* d_logits,
-                     uint8_t* d_cand, void* stream);
+                     uint16_t* d_cand, void* stream);
 
 /*
  * Immediate updates (Sec. 5.2.1). The tuple set is kept: an inserted rule goes to the
  * tuple with its own signature, else to the first tuple with the largest length sum
  * among those whose lengths are all <= the rule's (its prefixes are then checked in
  * the bucket scan); only if no tuple qualifies is a new tuple appended (the model
- * never predicts it; certification and the fallback still search it).
+ * never predicts it; certification and the fallback still search it; past the mask
+ * width's tuple limit, see tang_ruleset_conflict_mask_words, the batch fails with EINVAL).
  * A batch is validated as a whole before anything changes (all-or-nothing): insert
  * fails with EEXIST on a live or repeated id and EINVAL on a bad field; delete fails
  * with ENOTFOUND on an id that is not live. The device changes are enqueued on the

@@ -107,7 +107,7 @@ using namespace tang;
 size_t tang_ruleset_s::device_bytes() const {
     if (device == TANG_HOST_ONLY) return 0;
     return slots.size() * sizeof(Slot) + filter.size() * sizeof(uint32_t) +
-           (size_t)rec_cap * sizeof(Rec) + (nw > 1 ? (size_t)rec_cap * kMaskWords * 4 : 0) +
+           (size_t)rec_cap * sizeof(Rec) + (nw > 1 ? (size_t)rec_cap * nw * 4 : 0) +
            sizeof(TupleTable) +
            kStatCopies * sizeof(StatsDev) + model.bytes;
 }
@@ -229,10 +229,11 @@ int tang_ruleset_conflict_mask_words(tang_ruleset_t* rs, uint32_t id, uint32_t* 
     Rec r;
     TANG_HIP(hipMemcpy(&r, rs->d_recs + pos, sizeof r, hipMemcpyDeviceToHost));
     if (r.id != id) return fail(TANG_EINVAL, "record/handle mismatch");
-    uint32_t row[kMaskWords] = {r.cmask};
+    uint32_t row[kMaxWords] = {r.cmask};
     if (rs->nw > 1)
-        TANG_HIP(hipMemcpy(row, rs->d_cmask + (size_t)pos * kMaskWords, sizeof row, hipMemcpyDeviceToHost));
-    for (uint32_t w = 0; w < n_words; ++w) words[w] = w < kMaskWords ? row[w] : 0u;
+        TANG_HIP(hipMemcpy(row, rs->d_cmask + (size_t)pos * rs->nw, rs->nw * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost));
+    for (uint32_t w = 0; w < n_words; ++w) words[w] = w < rs->nw ? row[w] : 0u;
     return TANG_OK;
     TANG_GUARD_END
 }
@@ -326,14 +327,14 @@ static int check_classify(const tang_ruleset_t* rs, const void* hdr, const void*
 }
 
 static int run_search(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_io, size_t n,
-                      hipStream_t s, tang_stats_t* stats) {
+                      hipStream_t s, tang_stats_t* stats, const uint32_t* d_live = nullptr) {
     std::unique_lock<std::mutex> lk(rs->stats_mu, std::defer_lock);
     if (stats) {
         lk.lock();
         TANG_HIP(hipMemsetAsync(rs->d_stats, 0, kStatCopies * sizeof(StatsDev), s));
     }
     const int kcand = rs->model.loaded ? rs->model.topk : 0;
-    TANG_HIP(launch_classify(rs, d_hdr, d_io, n, kcand, s, stats != nullptr));
+    TANG_HIP(launch_classify(rs, d_hdr, d_io, n, kcand, s, stats != nullptr, d_live));
     if (stats) {
         StatsDev part[kStatCopies], h;
         std::memset(&h, 0, sizeof h);
@@ -393,9 +394,11 @@ static int classify_chunked(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint
 
 namespace tang {
 int classify_async(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id, size_t n,
-                   hipStream_t s, tang_stats_t* stats, bool allow_chunks) {
+                   hipStream_t s, tang_stats_t* stats, bool allow_chunks, const uint32_t* d_live) {
     int rc = check_classify(rs, d_hdr, d_rule_id, n);
     if (rc) return rc;
+    if (d_live && (stats || allow_chunks || rs->model.kind != 0))
+        return fail(TANG_EINVAL, "a live-count launch takes no stats, chunks or residual model");
     if (stats) std::memset(stats, 0, sizeof *stats);
     if (n == 0) return TANG_OK;
     TANG_HIP(hipSetDevice(rs->device));
@@ -406,8 +409,8 @@ int classify_async(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_r
         rc = classify_chunked(rs, d_hdr, d_rule_id, n, s, &done);
         if (rc || done) return rc;
     }
-    if (rs->model.loaded) TANG_HIP(launch_mlp(rs, d_hdr, n, d_rule_id, nullptr, nullptr, s));
-    return run_search(rs, d_hdr, d_rule_id, n, s, stats);
+    if (rs->model.loaded) TANG_HIP(launch_mlp(rs, d_hdr, n, d_rule_id, nullptr, nullptr, s, false, d_live));
+    return run_search(rs, d_hdr, d_rule_id, n, s, stats, d_live);
 }
 }  // namespace tang
 
@@ -450,7 +453,8 @@ int tang_search_host(const tang_ruleset_t* rs, const tang_header_t* hdr, const u
                      tang_stats_t* stats) {
     TANG_GUARD_BEGIN
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
-    if (kcand > TANG_MAX_TOPK) return fail(TANG_EINVAL, "kcand must be in 0..4");
+    if (kcand > (rs->sigs.size() > 256 ? 2u : (uint32_t)TANG_MAX_TOPK))
+        return fail(TANG_EINVAL, "kcand must be in 0..4 (0..2 above 256 tuples)");
     if (n && (!hdr || !rule_id || (kcand && !cand))) return fail(TANG_EINVAL, "NULL buffer");
     if (stats) std::memset(stats, 0, sizeof *stats);
     if (n == 0) return TANG_OK;
@@ -487,7 +491,7 @@ int tang_classify_host(tang_ruleset_t* rs, const tang_header_t* hdr, uint32_t* r
 }
 
 int tang_mlp_forward(tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n, float* d_logits,
-                     uint8_t* d_cand, void* stream) {
+                     uint16_t* d_cand, void* stream) {
     TANG_GUARD_BEGIN
     if (!rs) return fail(TANG_EINVAL, "NULL ruleset");
     if (rs->device == TANG_HOST_ONLY || !rs->model.loaded) return fail(TANG_EINVAL, "no model loaded");

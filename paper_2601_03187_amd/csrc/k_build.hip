@@ -160,19 +160,21 @@ __global__ void k_place_records(Rec* __restrict__ recs, const Rec* __restrict__ 
     recs[dst[i]] = stage[i];
 }
 
-__global__ void k_stage_masks(const uint32_t* __restrict__ cmask, const uint32_t* __restrict__ src,
-                              uint32_t n, uint32_t* __restrict__ stage) {
+__global__ void k_stage_masks(const uint32_t* __restrict__ cmask, uint32_t nw,
+                              const uint32_t* __restrict__ src, uint32_t n,
+                              uint32_t* __restrict__ stage) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * kMaskWords) return;
-    const uint32_t r = i / kMaskWords, w = i % kMaskWords, s = src[r];
-    stage[i] = (s & 0x80000000u) ? 0u : cmask[(size_t)s * kMaskWords + w];
+    if (i >= n * nw) return;
+    const uint32_t r = i / nw, w = i % nw, s = src[r];
+    stage[i] = (s & 0x80000000u) ? 0u : cmask[(size_t)s * nw + w];
 }
 
-__global__ void k_place_masks(uint32_t* __restrict__ cmask, const uint32_t* __restrict__ stage,
-                              const uint32_t* __restrict__ dst, uint32_t n) {
+__global__ void k_place_masks(uint32_t* __restrict__ cmask, uint32_t nw,
+                              const uint32_t* __restrict__ stage, const uint32_t* __restrict__ dst,
+                              uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * kMaskWords) return;
-    cmask[(size_t)dst[i / kMaskWords] * kMaskWords + i % kMaskWords] = stage[i];
+    if (i >= n * nw) return;
+    cmask[(size_t)dst[i / nw] * nw + i % nw] = stage[i];
 }
 
 __global__ void k_scatter_slots(Slot* __restrict__ slots, const uint32_t* __restrict__ idx,
@@ -189,8 +191,11 @@ hipError_t launch_conflict_build(const BoxDev* d_boxes, size_t n, Rec* d_recs, u
     const dim3 g((n + 255) / 256), b(256);
     if (nw == 1)
         hipLaunchKernelGGL(k_conflict_build<1>, g, b, 0, s, d_boxes, (uint32_t)n, d_recs, d_cmask, all_mask);
-    else
+    else if (nw == kMaskWords)
         hipLaunchKernelGGL(k_conflict_build<kMaskWords>, g, b, 0, s, d_boxes, (uint32_t)n, d_recs,
+                           d_cmask, all_mask);
+    else
+        hipLaunchKernelGGL(k_conflict_build<kMaxWords>, g, b, 0, s, d_boxes, (uint32_t)n, d_recs,
                            d_cmask, all_mask);
     return hipGetLastError();
 }
@@ -201,8 +206,11 @@ hipError_t launch_conflict_update(Rec* d_recs, uint32_t* d_cmask, uint32_t nw, u
     const dim3 g((rec_used + 255) / 256), b(256);
     if (nw == 1)
         hipLaunchKernelGGL(k_conflict_update<1>, g, b, 0, s, d_recs, d_cmask, rec_used, d_new_pos, n_new);
-    else
+    else if (nw == kMaskWords)
         hipLaunchKernelGGL(k_conflict_update<kMaskWords>, g, b, 0, s, d_recs, d_cmask, rec_used,
+                           d_new_pos, n_new);
+    else
+        hipLaunchKernelGGL(k_conflict_update<kMaxWords>, g, b, 0, s, d_recs, d_cmask, rec_used,
                            d_new_pos, n_new);
     return hipGetLastError();
 }
@@ -218,14 +226,14 @@ hipError_t launch_move_records(Rec* d_recs, const Rec* d_fresh, const uint32_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_move_masks(uint32_t* d_cmask, const uint32_t* d_src, const uint32_t* d_dst,
-                             uint32_t n, uint32_t* d_stage, hipStream_t s) {
+hipError_t launch_move_masks(uint32_t* d_cmask, uint32_t nw, const uint32_t* d_src,
+                             const uint32_t* d_dst, uint32_t n, uint32_t* d_stage, hipStream_t s) {
     if (!n) return hipSuccess;
-    const dim3 g((n * kMaskWords + 255) / 256), b(256);
-    hipLaunchKernelGGL(k_stage_masks, g, b, 0, s, d_cmask, d_src, n, d_stage);
+    const dim3 g((n * nw + 255) / 256), b(256);
+    hipLaunchKernelGGL(k_stage_masks, g, b, 0, s, d_cmask, nw, d_src, n, d_stage);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_place_masks, g, b, 0, s, d_cmask, d_stage, d_dst, n);
+    hipLaunchKernelGGL(k_place_masks, g, b, 0, s, d_cmask, nw, d_stage, d_dst, n);
     return hipGetLastError();
 }
 

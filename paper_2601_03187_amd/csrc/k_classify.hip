@@ -14,9 +14,10 @@
 // tuples whose bit is set. Random loads are what the search pays for (each one costs
 // an L2 request whatever its width), so the scan also reads only the first half of each
 // record and the second half only when a rule matches.
-// Candidates come packed in the output word (one byte per candidate) from the MLP.
-// Tuple spaces of more than 32 tuples (up to 256) use the same steps over eight-word
-// tuple masks, with conflict masks in a side array.
+// Candidates come packed in the output word from the MLP (one byte per candidate, 16
+// bits above 256 tuples). Tuple spaces of more than 32 tuples use the same steps over
+// multiword tuple masks (8 words up to 256 tuples, 16 up to 512), with conflict masks in
+// a side array.
 #include <type_traits>
 
 #include "tang_internal.hpp"
@@ -164,9 +165,10 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
-// NW: conflict-mask words (1 for at most 32 tuples, kMaskWords for up to 256). Tuple
-// sets are NW-word bit masks (word t / 32, bit t % 32); group sets one word (at most 32
-// groups) or two (64).
+// NW: conflict-mask words (1 for at most 32 tuples, kMaskWords for up to 256, kMaxWords
+// above). Tuple sets are NW-word bit masks (word t / 32, bit t % 32); group sets one
+// word (at most 32 groups) or two (64). The best-key prefixes stay in LDS up to 256
+// tuples; above, the one row a lane needs is read from the tuple table.
 template <bool STATS, int NW>
 __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                                                   uint32_t* __restrict__ out, uint32_t n,
@@ -175,25 +177,31 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
                                                   const uint32_t* __restrict__ cmask_rows,
                                                   const uint2* __restrict__ filter,
                                                   const TupleTable* __restrict__ ttg, int kcand,
-                                                  StatsDev* __restrict__ st) {
+                                                  StatsDev* __restrict__ st,
+                                                  const uint32_t* __restrict__ live) {
     constexpr uint32_t NT = 32u * NW;
     constexpr int NG = NW == 1 ? 32 : kMaxGroups;   // groups: at most one per tuple
+    constexpr bool PREFIX_LDS = NW <= kMaskWords;
+    constexpr uint32_t CB = NW > kMaskWords ? 16u : 8u;   // bits per packed candidate
     using GMask = typename std::conditional<NW == 1, uint32_t, unsigned long long>::type;
     __shared__ TupleDev s_t[NT];
     __shared__ uint2 s_rank[NT];  // best keys in ascending order
-    __shared__ uint32_t s_prefix[NT + 1][NW];
+    __shared__ uint32_t s_prefix[PREFIX_LDS ? NT + 1 : 1][NW];
     __shared__ uint32_t s_all[NW], s_nog[NW];
     __shared__ uint32_t s_gid[NT];
     __shared__ uint32_t s_gkey[NG];
     __shared__ uint32_t s_gmask[NG][NW];
     __shared__ uint32_t s_misc[4];
     const int tid = threadIdx.x;
+    if (live) n = min(n, *live);
+    if (blockIdx.x * 256u >= n) return;   // uniform over the block (a live count below the grid)
     for (uint32_t k = tid; k < NT; k += 256u) {
         s_t[k] = ttg->t[k];
         s_rank[k] = make_uint2(ttg->rank_prio[k], ttg->rank_id[k]);
         s_gid[k] = ttg->gid[k];
     }
-    for (uint32_t k = tid; k < (NT + 1) * NW; k += 256u) s_prefix[k / NW][k % NW] = ttg->prefix[k / NW][k % NW];
+    if constexpr (PREFIX_LDS)
+        for (uint32_t k = tid; k < (NT + 1) * NW; k += 256u) s_prefix[k / NW][k % NW] = ttg->prefix[k / NW][k % NW];
     for (uint32_t k = tid; k < (uint32_t)NG * NW; k += 256u) s_gmask[k / NW][k % NW] = ttg->gmask[k / NW][k % NW];
     if (tid < NG) s_gkey[tid] = ttg->gkey[tid];
     if (tid < NW) {
@@ -234,7 +242,7 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
         if (kcand > 0) {
             const uint32_t cp = out[i];
             for (int c = 0; c < kcand; ++c) {
-                const uint32_t t = (cp >> (8 * c)) & 0xFFu;
+                const uint32_t t = (cp >> (CB * c)) & ((1u << CB) - 1u);
                 if (c == 0) c0 = t;
                 if (t >= ntup) continue;
                 uint32_t& pw = probed[NW == 1 ? 0 : t >> 5];
@@ -293,8 +301,20 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
             for (uint32_t step = NT; step > 0; step >>= 1)
                 if (k + step <= ntup && kless(s_rank[k + step - 1].x, s_rank[k + step - 1].y, b.prio, b.id))
                     k += step;
+            if constexpr (PREFIX_LDS) {
 #pragma unroll
-            for (int w = 0; w < NW; ++w) todo[w] &= s_prefix[k][w];
+                for (int w = 0; w < NW; ++w) todo[w] &= s_prefix[k][w];
+            } else {
+                const uint4* row = reinterpret_cast<const uint4*>(ttg->prefix[k]);
+#pragma unroll
+                for (int q = 0; q < NW / 4; ++q) {
+                    const uint4 m = row[q];
+                    todo[4 * q] &= m.x;
+                    todo[4 * q + 1] &= m.y;
+                    todo[4 * q + 2] &= m.z;
+                    todo[4 * q + 3] &= m.w;
+                }
+            }
         }
     }
     // Phase 1: the groups the remaining tuples need (the first candidate's block is
@@ -523,8 +543,9 @@ __global__ __launch_bounds__(256) void k_classify(const uint4* __restrict__ hdr,
 }  // namespace
 
 hipError_t launch_classify(const tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_out,
-                           size_t n, int kcand, hipStream_t s, bool stats) {
+                           size_t n, int kcand, hipStream_t s, bool stats, const uint32_t* d_live) {
     const size_t chunk = (size_t)1 << 30;
+    if (d_live && n > chunk) return hipErrorInvalidValue;
     for (size_t base = 0; base < n; base += chunk) {
         const uint32_t m = (uint32_t)std::min(chunk, n - base);
         const dim3 grid((m + 255) / 256), block(256);
@@ -532,14 +553,17 @@ hipError_t launch_classify(const tang_ruleset_t* rs, const tang_header_t* d_hdr,
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, grid, block, 0, s, h, d_out + base, m, rs->d_slots, rs->d_recs,
                                rs->d_cmask, reinterpret_cast<const uint2*>(rs->d_filter), rs->d_tt,
-                               kcand, rs->d_stats);
+                               kcand, rs->d_stats, d_live);
         };
         if (rs->nw == 1) {
             if (stats) go(k_classify<true, 1>);
             else go(k_classify<false, 1>);
-        } else {
+        } else if (rs->nw == kMaskWords) {
             if (stats) go(k_classify<true, kMaskWords>);
             else go(k_classify<false, kMaskWords>);
+        } else {
+            if (stats) go(k_classify<true, kMaxWords>);
+            else go(k_classify<false, kMaxWords>);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

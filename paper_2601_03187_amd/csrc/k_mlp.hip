@@ -166,22 +166,31 @@ __device__ __forceinline__ u32x4 bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uin
     return __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0);
 }
 
+//
+// An LDS read takes one address register plus an immediate offset below 64 KB. Each
+// layer's fragments are therefore addressed through 64 KB windows: `win[w]` holds w as
+// a value the compiler cannot see (set once per tile), so the window's base becomes one
+// register per window instead of one address addition per fragment read past 64 KB.
 template <bool IN_LDS, typename F>
 __device__ __forceinline__ F ldf(const F* lds, __amdgpu_buffer_rsrc_t r, uint32_t frag, uint32_t lane,
-                                 uint32_t sbase) {
+                                 uint32_t sbase, const uint32_t* win) {
+    constexpr uint32_t FPW = 65536u / (64u * (uint32_t)sizeof(F));   // fragments per window
     if constexpr (sizeof(F) == 32) {
         u32x4 lo, hi;
         if constexpr (IN_LDS) {
-            const u32x4* p = reinterpret_cast<const u32x4*>(lds);
-            lo = p[frag * 128 + lane + sbase];
-            hi = p[frag * 128 + 64 + lane + sbase];
+            const u32x4* p = reinterpret_cast<const u32x4*>(reinterpret_cast<const char*>(lds) +
+                                                            win[frag / FPW] * 65536u) + lane;
+            lo = p[(frag % FPW) * 128];
+            hi = p[(frag % FPW) * 128 + 64];
         } else {
             lo = __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16u + sbase, frag * 2048u, 0);
             hi = __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16u + sbase, frag * 2048u + 1024u, 0);
         }
         return (F){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     } else {
-        if constexpr (IN_LDS) return lds[frag * 64 + lane + sbase];  // sbase: opaque 0, see below
+        if constexpr (IN_LDS)
+            return reinterpret_cast<const F*>(reinterpret_cast<const char*>(lds) +
+                                              win[frag / FPW] * 65536u)[(frag % FPW) * 64 + lane];
         else return bload(r, lane * (uint32_t)sizeof(F) + sbase, frag * 64u * (uint32_t)sizeof(F), (F*)nullptr);
     }
 }
@@ -223,14 +232,14 @@ __device__ __forceinline__ void epi_hidden(const f4 (&acc)[NT], int mt, const fl
 
 constexpr int kNoClass = 1 << 20;  // an empty or removed top-k slot (above every class)
 
-// OUTB: most blocks of 32 output classes (1, or 8 for up to 256 tuples; the W3 fragments
+// OUTB: most blocks of 32 output classes (1, or 16 for up to 512 tuples; the W3 fragments
 // of a multi-block model are read from L2).
 template <int PREC, int H, int NT, int LDSM, int WAVES, int OUTB>
 __global__ __launch_bounds__(64 * WAVES) void k_mlp(
     const uint4* __restrict__ hdr, uint32_t n, const typename FragT<PREC>::T* __restrict__ w1,
     const typename FragT<PREC>::T* __restrict__ w2, const typename FragT<PREC>::T* __restrict__ w3,
     const u32x4* __restrict__ w1x3, const float* __restrict__ bias_g, MlpArgs a, uint32_t* __restrict__ cand,
-    float* __restrict__ logits, uint8_t* __restrict__ cand8) {
+    float* __restrict__ logits, uint16_t* __restrict__ cand16, const uint32_t* __restrict__ live) {
     using F = typename FragT<PREC>::T;
     constexpr int KB = FragT<PREC>::KB;
     constexpr int KBN1 = kInPad / KB, KBNH = H / KB, MTH = H / 16;
@@ -240,6 +249,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
     static_assert(OUTB == 1 || !(LDSM & 4), "multi-block output layers stay in L2");
     // output tiles per MFMA group in layer 2 (more when each tile is only 1-2 MFMAs)
     constexpr int TG = PREC == TANG_FP8 ? 2 : PREC == TANG_BF16 ? 2 : 1;
+
+    if (live) n = min(n, *live);
+    // a workgroup without a tile leaves before staging the weights (uniform over the block)
+    if (blockIdx.x * WAVES >= (n + 16 * NT - 1) / (16 * NT)) return;
 
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     F* s1 = reinterpret_cast<F*>(smem);
@@ -277,6 +290,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
         // of the tile loop and run out of registers
         uint32_t sbase = 0;
         asm volatile("" : "+s"(sbase));
+        uint32_t win[3] = {0u, 1u, 2u};   // LDS windows (see ldf); 160 KB of LDS needs three
+        asm volatile("" : "+v"(win[0]), "+v"(win[1]), "+v"(win[2]));
+        // biases and the bit table sit past 64 KB too: their reads go through an opaque
+        // base register as well
+        const float* sbv = reinterpret_cast<const float*>(reinterpret_cast<const char*>(sb) + win[0] * 65536u);
+        const unsigned char* stv = stab + win[0] * 65536u;
         uint4 hv[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
@@ -295,7 +314,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) xb[kb][nt] = Bits<TANG_BF16>::get(hv[nt], kb, g, stab);
+                for (int nt = 0; nt < NT; ++nt) xb[kb][nt] = Bits<TANG_BF16>::get(hv[nt], kb, g, stv);
             const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
                 (void*)w1x3, 0, (uint32_t)(MTH * 12 * 64 * 16), 0x00020000);
 #pragma unroll
@@ -305,14 +324,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                 for (int f = 0; f < 12; ++f)
                     wf[f] = bload(rx, lane * 16u + sbase, (uint32_t)((mt * 12 + f) * 1024), (u32x4*)nullptr);
                 f4 acc[NT];
-                const f4 b0 = acc_init<PREC>(sb, mt, g);
+                const f4 b0 = acc_init<PREC>(sbv, mt, g);
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[nt] = b0;
 #pragma unroll
                 for (int f = 0; f < 12; ++f)
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) acc[nt] = mma(wf[f], xb[f / 3][nt], acc[nt]);
-                epi_hidden<PREC, NT, KBNH>(acc, mt, sb, a.hs[0], g, a0);
+                epi_hidden<PREC, NT, KBNH>(acc, mt, sbv, a.hs[0], g, a0);
                 __builtin_amdgcn_sched_barrier(0);
             }
         } else {
@@ -324,28 +343,28 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
 #pragma unroll
         for (int kb = 0; kb < KBN1_USED; ++kb)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) bits[kb][nt] = Bits<PREC>::get(hv[nt], kb, g, stab);
+            for (int nt = 0; nt < NT; ++nt) bits[kb][nt] = Bits<PREC>::get(hv[nt], kb, g, stv);
         if constexpr (!(LDSM & 1)) {
 #pragma unroll
-            for (int kb = 0; kb < KBN1_USED; ++kb) pre[kb] = ldf<false>(s1, r1, kb, lane, sbase);
+            for (int kb = 0; kb < KBN1_USED; ++kb) pre[kb] = ldf<false>(s1, r1, kb, lane, sbase, win);
         }
 #pragma unroll
         for (int mt = 0; mt < MTH; ++mt) {
             F cur[KBN1_USED];
 #pragma unroll
             for (int kb = 0; kb < KBN1_USED; ++kb) {
-                if constexpr ((LDSM & 1) != 0) cur[kb] = ldf<true>(s1, r1, mt * KBN1 + kb, lane, sbase);
+                if constexpr ((LDSM & 1) != 0) cur[kb] = ldf<true>(s1, r1, mt * KBN1 + kb, lane, sbase, win);
                 else cur[kb] = pre[kb];
             }
             if constexpr (!(LDSM & 1)) {
                 if (mt + 1 < MTH) {
 #pragma unroll
                     for (int kb = 0; kb < KBN1_USED; ++kb)
-                        pre[kb] = ldf<false>(s1, r1, (mt + 1) * KBN1 + kb, lane, sbase);
+                        pre[kb] = ldf<false>(s1, r1, (mt + 1) * KBN1 + kb, lane, sbase, win);
                 }
             }
             f4 acc[NT];
-            const f4 b0 = acc_init<PREC>(sb, mt, g);
+            const f4 b0 = acc_init<PREC>(sbv, mt, g);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[nt] = b0;
 #pragma unroll
@@ -353,20 +372,37 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[nt] = mma(cur[kb], bits[kb][nt], acc[nt]);
             }
-            epi_hidden<PREC, NT, KBNH>(acc, mt, sb, a.hs[0], g, a0);
+            epi_hidden<PREC, NT, KBNH>(acc, mt, sbv, a.hs[0], g, a0);
             // keep the scheduler from hoisting every tile's fragment loads (register blow-up)
             __builtin_amdgcn_sched_barrier(0);
         }
         }
         // layer 2: H -> H, TG output tiles per group: all MFMAs of the group are issued
-        // before its epilogues, so the matrix pipe has independent work while results land
+        // before its epilogues, so the matrix pipe has independent work while results land.
+        // With one block of classes the output layer runs inside this loop: as soon as
+        // the group completes a K block of layer 3, that block's MFMAs are issued, so the
+        // second hidden layer never has to be held whole (its K blocks are consumed in
+        // the same ascending order as an unfused layer 3 would take them).
         F a1[KBNH][NT];
+        f4 z[2][NT];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) z[mt][nt] = (f4){0, 0, 0, 0};
+        auto layer3_block = [&](int kb) {
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                const F A = ldf<(LDSM & 4) != 0>(s3, r3, mt * KBNH + kb, lane, sbase, win);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) z[mt][nt] = mma(A, a1[kb][nt], z[mt][nt]);
+            }
+        };
 #pragma unroll
         for (int mt0 = 0; mt0 < MTH; mt0 += TG) {
             f4 acc[TG][NT];
 #pragma unroll
             for (int u = 0; u < TG; ++u) {
-                const f4 b0 = acc_init<PREC>(sb + H, mt0 + u, g);
+                const f4 b0 = acc_init<PREC>(sbv + H, mt0 + u, g);
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[u][nt] = b0;
             }
@@ -374,14 +410,28 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
             for (int kb = 0; kb < KBNH; ++kb) {
 #pragma unroll
                 for (int u = 0; u < TG; ++u) {
-                    const F A = ldf<(LDSM & 2) != 0>(s2, r2, (mt0 + u) * KBNH + kb, lane, sbase);
+                    const F A = ldf<(LDSM & 2) != 0>(s2, r2, (mt0 + u) * KBNH + kb, lane, sbase, win);
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) acc[u][nt] = mma(A, a0[kb][nt], acc[u][nt]);
                 }
             }
 #pragma unroll
             for (int u = 0; u < TG; ++u)
-                epi_hidden<PREC, NT, KBNH>(acc[u], mt0 + u, sb + H, a.hs[1], g, a1);
+                epi_hidden<PREC, NT, KBNH>(acc[u], mt0 + u, sbv + H, a.hs[1], g, a1);
+            if constexpr (OUTB == 1) {
+                // output tile mt feeds K block mt / (KB / 16) (KB >= 16), or the four
+                // blocks 4 mt .. 4 mt + 3 (FP32, KB = 4)
+#pragma unroll
+                for (int u = 0; u < TG; ++u) {
+                    const int mt = mt0 + u;
+                    if constexpr (KB >= 16) {
+                        if ((mt + 1) % (KB / 16) == 0) layer3_block(mt / (KB / 16));
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 16 / KB; ++q) layer3_block((16 / KB) * mt + q);
+                    }
+                }
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
         // layer 3: H -> C in blocks of 32 classes (two 16-row tiles). With one block each
@@ -390,7 +440,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
         // the lower class, as classes ascend block by block; there a NaN or -inf score
         // counts as -FLT_MAX, so every real class beats an empty slot and a padded class).
         // With one block a NaN score counts as -inf and ties go to the lower class.
-        const float* sb3 = sb + 2 * H;
+        const float* sb3 = sbv + 2 * H;
         constexpr int KL = OUTB == 1 ? 8 : 4;
         float v[NT][KL];
         int cl[NT][KL];
@@ -406,18 +456,19 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
         const int ncb = OUTB == 1 ? 1 : (C + 31) / 32;
 #pragma unroll 1
         for (int cb = 0; cb < ncb; ++cb) {
-            f4 z[2][NT];
+            if constexpr (OUTB > 1) {
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt) {
+                for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) z[mt][nt] = (f4){0, 0, 0, 0};
+                    for (int nt = 0; nt < NT; ++nt) z[mt][nt] = (f4){0, 0, 0, 0};
 #pragma unroll
-                for (int kb = 0; kb < KBNH; ++kb) {
-                    const F A = ldf<(LDSM & 4) != 0>(s3, r3, (2 * cb + mt) * KBNH + kb, lane, sbase);
+                    for (int kb = 0; kb < KBNH; ++kb) {
+                        const F A = ldf<(LDSM & 4) != 0>(s3, r3, (2 * cb + mt) * KBNH + kb, lane, sbase, win);
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) z[mt][nt] = mma(A, a1[kb][nt], z[mt][nt]);
+                        for (int nt = 0; nt < NT; ++nt) z[mt][nt] = mma(A, a1[kb][nt], z[mt][nt]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                __builtin_amdgcn_sched_barrier(0);
             }
             // scores; the running top-k keeps topk slots (1, 2, or 4 for 3 and 4; a uniform
             // branch per block picks the count)
@@ -476,8 +527,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                     const int oc = __shfl_xor(bc, o, 64);
                     if (ov > bv || (ov == bv && oc < bc)) { bv = ov; bc = oc; }
                 }
-                packed |= (uint32_t)bc << (8 * k);
-                if (cand8 && g == 0 && pkt < n) cand8[(size_t)pkt * a.topk + k] = (uint8_t)bc;
+                packed |= (uint32_t)bc << (cand_bits(C) * k);
+                if (cand16 && g == 0 && pkt < n) cand16[(size_t)pkt * a.topk + k] = (uint16_t)bc;
 #pragma unroll
                 for (int q = 0; q < KL; ++q)
                     if (cl[nt][q] == bc) v[nt][q] = -INFINITY;
@@ -562,9 +613,9 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
     if ((int)d->dims[2] != H || (H != 128 && H != 256))
         return fail(TANG_EINVAL, "hidden widths must be equal and 128 or 256");
     if ((int)d->dims[3] != C || C < 1 || C > TANG_MAX_TUPLES)
-        return fail(TANG_EINVAL, "output width must equal the number of tuples (1..256)");
-    if (d->topk < 1 || d->topk > TANG_MAX_TOPK || (int)d->topk > C)
-        return fail(TANG_EINVAL, "topk must be in 1..min(4, C)");
+        return fail(TANG_EINVAL, "output width must equal the number of tuples");
+    if (d->topk < 1 || (int)d->topk > max_topk(C))
+        return fail(TANG_EINVAL, "topk must be in 1..min(4, C), 1..2 above 256 tuples");
     if (p != TANG_FP32 && p != TANG_BF16 && p != TANG_FP8) return fail(TANG_EINVAL, "bad precision");
     if (p == TANG_FP8) {
         if (!act_scales) return fail(TANG_EINVAL, "FP8 needs act_scales");
@@ -682,7 +733,7 @@ namespace {
 
 template <int PREC, int H, int NT, int LDSM, int WAVES = 8, int OUTB = 1>
 hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, uint32_t* cand,
-                    float* logits, uint8_t* cand8, hipStream_t s) {
+                    float* logits, uint16_t* cand16, hipStream_t s, const uint32_t* live) {
     using F = typename FragT<PREC>::T;
     constexpr int KB = FragT<PREC>::KB;
     constexpr size_t n1 = (H / 16) * (kInPad / KB) * 64, n2 = (H / 16) * (H / KB) * 64,
@@ -717,48 +768,55 @@ hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, u
     for (int l = 0; l < 2; ++l) a.hs[l] = m.deq[l] * m.inv_a[l + 1];
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WAVES), lds, s,
                        reinterpret_cast<const uint4*>(d_hdr), n, (const F*)m.w[0], (const F*)m.w[1],
-                       (const F*)m.w[2], (const u32x4*)m.w1x3, m.bias, a, cand, logits, cand8);
+                       (const F*)m.w[2], (const u32x4*)m.w1x3, m.bias, a, cand, logits, cand16, live);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
-                      uint32_t* d_cand_packed, float* d_logits, uint8_t* d_cand8, hipStream_t s, bool beside_search) {
+                      uint32_t* d_cand_packed, float* d_logits, uint16_t* d_cand16, hipStream_t s, bool beside_search,
+                      const uint32_t* d_live) {
     const ModelDev& m = rs->model;
-    if (m.kind == 1) return launch_resnet(rs, d_hdr, n, d_cand_packed, d_logits, d_cand8, s);
+    if (m.kind == 1) {
+        if (d_live) return hipErrorInvalidValue;
+        return launch_resnet(rs, d_hdr, n, d_cand_packed, d_logits, d_cand16, s);
+    }
     const size_t chunk = (size_t)1 << 30;
+    if (d_live && n > chunk) return hipErrorInvalidValue;
     for (size_t base = 0; base < n; base += chunk) {
         const uint32_t k = (uint32_t)std::min(chunk, n - base);
         const tang_header_t* h = d_hdr + base;
         uint32_t* c = d_cand_packed ? d_cand_packed + base : nullptr;
         float* lg = d_logits ? d_logits + base * (size_t)m.n_out : nullptr;
-        uint8_t* c8 = d_cand8 ? d_cand8 + base * (size_t)m.topk : nullptr;
+        uint16_t* c8 = d_cand16 ? d_cand16 + base * (size_t)m.topk : nullptr;
         hipError_t e;
         // LDSM: which layers' fragments sit in LDS (bit l = layer l) -- 160 KB per CU.
         // FP32 reads its input layer's BF16 planes from L2 (bit 0 unused).
-        // BF16 and FP8 at H = 256 run 12 waves per CU (3 per SIMD) on their own, and 8
-        // (2 per SIMD) beside a chunked classify's search, whose waves then fit next to
-        // them: alone 12 are faster (BF16 2.99 -> 2.73 ms, FP8 2.20 -> 1.87 ms per 16M
-        // headers), overlapped 8 are (BF16 3,390 vs 3,190 Mpps, FP8 3,970 vs 3,770).
-        // More than 32 tuples: up to 8 blocks of 32 classes, W3 read from L2.
+        // At H = 256 the predictor alone runs BF16 as 8 waves of 64 headers (NT = 4: each
+        // weight fragment read from LDS serves four header tiles; 254 VGPRs) and FP8 as 12
+        // waves of 32; beside a chunked classify's search both run 8 waves of 32 headers,
+        // so that search waves fit on every SIMD next to them (measured per 16M headers:
+        // BF16 alone 2.56 ms with 12 waves of 32, 2.44 ms with 8 of 64; chunked classify
+        // unchanged by the alone variant).
+        // More than 32 tuples: up to 16 blocks of 32 classes, W3 read from L2.
         const bool wide = m.n_out > kOutPad;
         if (wide) {
-            if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 2, 8, 8>(m, h, k, c, lg, c8, s);
-            else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0, 8, 8>(m, h, k, c, lg, c8, s);
-            else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 3, 8, 8>(m, h, k, c, lg, c8, s);
-            else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 2, 8, 8>(m, h, k, c, lg, c8, s);
-            else if (m.hidden == 128) e = launch_t<TANG_FP8, 128, 2, 3, 8, 8>(m, h, k, c, lg, c8, s);
-            else e = launch_t<TANG_FP8, 256, 2, 3, 8, 8>(m, h, k, c, lg, c8, s);
+            if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 2, 8,16>(m, h, k, c, lg, c8, s, d_live);
+            else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0, 8,16>(m, h, k, c, lg, c8, s, d_live);
+            else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 3, 8,16>(m, h, k, c, lg, c8, s, d_live);
+            else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 2, 8,16>(m, h, k, c, lg, c8, s, d_live);
+            else if (m.hidden == 128) e = launch_t<TANG_FP8, 128, 2, 3, 8,16>(m, h, k, c, lg, c8, s, d_live);
+            else e = launch_t<TANG_FP8, 256, 2, 3, 8,16>(m, h, k, c, lg, c8, s, d_live);
         }
-        else if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 6>(m, h, k, c, lg, c8, s);
-        else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0>(m, h, k, c, lg, c8, s);
-        else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 7>(m, h, k, c, lg, c8, s);
-        else if (m.prec == TANG_BF16 && beside_search) e = launch_t<TANG_BF16, 256, 2, 6, 8>(m, h, k, c, lg, c8, s);
-        else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 2, 6, 12>(m, h, k, c, lg, c8, s);
-        else if (m.hidden == 128) e = launch_t<TANG_FP8, 128, 2, 7>(m, h, k, c, lg, c8, s);
-        else if (beside_search) e = launch_t<TANG_FP8, 256, 2, 7, 8>(m, h, k, c, lg, c8, s);
-        else e = launch_t<TANG_FP8, 256, 2, 7, 12>(m, h, k, c, lg, c8, s);
+        else if (m.prec == TANG_FP32 && m.hidden == 128) e = launch_t<TANG_FP32, 128, 2, 6>(m, h, k, c, lg, c8, s, d_live);
+        else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0>(m, h, k, c, lg, c8, s, d_live);
+        else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 7>(m, h, k, c, lg, c8, s, d_live);
+        else if (m.prec == TANG_BF16 && beside_search) e = launch_t<TANG_BF16, 256, 2, 6, 8>(m, h, k, c, lg, c8, s, d_live);
+        else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 4, 6, 8>(m, h, k, c, lg, c8, s, d_live);
+        else if (m.hidden == 128) e = launch_t<TANG_FP8, 128, 2, 7>(m, h, k, c, lg, c8, s, d_live);
+        else if (beside_search) e = launch_t<TANG_FP8, 256, 2, 7, 8>(m, h, k, c, lg, c8, s, d_live);
+        else e = launch_t<TANG_FP8, 256, 2, 7, 12>(m, h, k, c, lg, c8, s, d_live);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_res_out(const uint16_t* __restrict__ in
                                                  const float* __restrict__ bias, uint32_t m,
                                                  int C, int topk, uint32_t* __restrict__ cand,
                                                  float* __restrict__ logits,
-                                                 uint8_t* __restrict__ cand8) {
+                                                 uint16_t* __restrict__ cand16) {
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u, g = lane >> 4, r = lane & 15u;
     const uint32_t p0 = (blockIdx.x * 4u + wave) * 64u;
     const int ncb = (C + 31) / 32;
@@ -316,8 +316,8 @@ __global__ __launch_bounds__(256) void k_res_out(const uint16_t* __restrict__ in
                 const int oc = __shfl_xor(bc, o, 64);
                 if (ov > bv || (ov == bv && oc < bc)) { bv = ov; bc = oc; }
             }
-            packed |= (uint32_t)bc << (8 * k);
-            if (cand8 && g == 0 && pkt < m) cand8[(size_t)pkt * topk + k] = (uint8_t)bc;
+            packed |= (uint32_t)bc << (cand_bits(C) * k);
+            if (cand16 && g == 0 && pkt < m) cand16[(size_t)pkt * topk + k] = (uint16_t)bc;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (cl[nt][q] == bc) { v[nt][q] = -INFINITY; cl[nt][q] = 1 << 20; }
@@ -344,8 +344,8 @@ int resnet_prepare(tang_ruleset_t* rs, const tang_resnet_desc_t* d, const float*
     if (d->n_blocks < 1 || d->n_blocks > 16) return fail(TANG_EINVAL, "n_blocks must be in 1..16");
     if ((int)d->n_out != C || C < 1 || C > TANG_MAX_TUPLES)
         return fail(TANG_EINVAL, "output width must equal the number of tuples (1..256)");
-    if (d->topk < 1 || d->topk > TANG_MAX_TOPK || (int)d->topk > C)
-        return fail(TANG_EINVAL, "topk must be in 1..min(4, C)");
+    if (d->topk < 1 || (int)d->topk > max_topk(C))
+        return fail(TANG_EINVAL, "topk must be in 1..min(4, C), 1..2 above 256 tuples");
     if (p != TANG_BF16) return fail(TANG_EINVAL, "the residual model runs in BF16");
     const int nb = (int)d->n_blocks, L = 2 + 2 * nb;
     for (int l = 0; l < L; ++l)
@@ -398,7 +398,7 @@ int resnet_prepare(tang_ruleset_t* rs, const tang_resnet_desc_t* d, const float*
 // The workspace is shared by every call on this ruleset: each call's launches wait for
 // the previous call's (an event), whatever stream either used.
 hipError_t launch_resnet(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
-                         uint32_t* cand, float* logits, uint8_t* cand8, hipStream_t s) {
+                         uint32_t* cand, float* logits, uint16_t* cand16, hipStream_t s) {
     const ModelDev& m = rs->model;
     std::lock_guard<std::mutex> lk(rs->ws_mu);
     hipError_t e = hipSuccess;
@@ -430,7 +430,7 @@ hipError_t launch_resnet(const tang_ruleset_t* rs, const tang_header_t* d_hdr, s
         hipLaunchKernelGGL(k_res_out, dim3((c + 255) / 256), dim3(256), 0, s, X, wout, bout, c,
                            m.n_out, m.topk, cand ? cand + base : nullptr,
                            logits ? logits + base * (size_t)m.n_out : nullptr,
-                           cand8 ? cand8 + base * (size_t)m.topk : nullptr);
+                           cand16 ? cand16 + base * (size_t)m.topk : nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -75,6 +75,7 @@ int search_host(const tang_ruleset_t* rs, const tang_header_t* hdr, const uint32
                 uint32_t* out, size_t n, uint32_t kcand, uint32_t threads, bool exact,
                 tang_stats_t* stats) {
     const uint32_t ntup = (uint32_t)rs->sigs.size();
+    const uint32_t cb = cand_bits((int)ntup);   // as packed by the predictor (see tang_predict)
     std::vector<uint32_t> order(ntup);
     for (uint32_t t = 0; t < ntup; ++t) order[t] = t;
     std::stable_sort(order.begin(), order.end(),
@@ -95,7 +96,7 @@ int search_host(const tang_ruleset_t* rs, const tang_header_t* hdr, const uint32
                 return false;
             };
             for (uint32_t k = 0; k < kcand; ++k) {
-                const uint32_t t = (cand[i] >> (8 * k)) & 0xFFu;
+                const uint32_t t = (cand[i] >> (cb * k)) & ((1u << cb) - 1u);
                 if (k == 0) c0 = t;
                 if (t >= ntup || was_probed(t)) continue;
                 probed[n_probed++] = t;

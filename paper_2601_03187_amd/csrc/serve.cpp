@@ -7,6 +7,10 @@
 // and staging bytes in flight stay within the configured limits, copies their headers
 // in, replays the HIP graph captured for (ruleset, batch size class, slot), copies the
 // results out and records an event. Completed slots hand results to their requests.
+// A graph is recorded for the largest batch of its size class (a power of two); the
+// batch's real header count travels in the same host-to-device copy as its headers (the
+// first 16 bytes of the slot's staging) and the kernels read it from there, so a batch
+// costs the work of its own headers, not of its class.
 // Requests that arrive while others are on the GPU are admitted as slots and budget
 // free up, so batches of different requests and rulesets overlap on the device.
 #include <chrono>
@@ -40,10 +44,15 @@ struct ReqState {
 struct StreamSlot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
-    tang_header_t* h_hdr = nullptr;  // pinned
+    // staging of max_batch + 1 headers: element 0 carries the live count in its first
+    // word, the batch's headers follow
+    tang_header_t* h_buf = nullptr;  // pinned
     uint32_t* h_out = nullptr;       // pinned
-    tang_header_t* d_hdr = nullptr;
+    tang_header_t* d_buf = nullptr;
     uint32_t* d_out = nullptr;
+    tang_header_t* h_hdr() const { return h_buf + 1; }
+    tang_header_t* d_hdr() const { return d_buf + 1; }
+    const uint32_t* d_live() const { return reinterpret_cast<const uint32_t*>(d_buf); }
     bool busy = false;
     size_t total = 0;
     std::vector<std::shared_ptr<ReqState>> reqs;
@@ -103,7 +112,7 @@ int tang_server_s::graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uin
     }
     StreamSlot& s = slots[si];
     TANG_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeRelaxed));
-    int rc = classify_async(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr, false);
+    int rc = classify_async(rs, s.d_hdr(), s.d_out, cls, s.stream, nullptr, false, s.d_live());
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s.stream, &graph);
     if (rc) {
@@ -131,15 +140,18 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, tang_ruleset_t* rs, bool wa
     size_t off = 0;
     for (auto& r : batch) {
         s.offs.push_back(off);
-        std::memcpy(s.h_hdr + off, r->hdr, r->n * sizeof(tang_header_t));
+        std::memcpy(s.h_hdr() + off, r->hdr, r->n * sizeof(tang_header_t));
         off += r->n;
     }
     size_t cls = 32;
     while (cls < total) cls <<= 1;
-    TANG_HIP(hipMemcpyAsync(s.d_hdr, s.h_hdr, total * sizeof(tang_header_t), hipMemcpyHostToDevice,
-                            s.stream));
+    const uint32_t live = (uint32_t)total;   // total <= max_batch, a 32-bit value
+    s.h_buf[0] = tang_header_t{};
+    std::memcpy(&s.h_buf[0], &live, sizeof live);
+    TANG_HIP(hipMemcpyAsync(s.d_buf, s.h_buf, (total + 1) * sizeof(tang_header_t),
+                            hipMemcpyHostToDevice, s.stream));
     if (!warm) {  // first use: eager call sets up kernel attributes before any capture
-        int rc = classify_async(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr, false);
+        int rc = classify_async(rs, s.d_hdr(), s.d_out, total, s.stream, nullptr, false);
         if (rc) return rc;
         TANG_HIP(hipStreamSynchronize(s.stream));
     }
@@ -151,7 +163,7 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, tang_ruleset_t* rs, bool wa
         if (rc) return rc;
         TANG_HIP(hipGraphLaunch(exec, s.stream));
     } else {
-        int rc = classify_async(rs, s.d_hdr, s.d_out, cls, s.stream, nullptr, false);
+        int rc = classify_async(rs, s.d_hdr(), s.d_out, total, s.stream, nullptr, false);
         if (rc) return rc;
     }
     TANG_HIP(hipMemcpyAsync(s.h_out, s.d_out, total * sizeof(uint32_t), hipMemcpyDeviceToHost,
@@ -256,9 +268,9 @@ static void free_server(tang_server_t* srv) {
         if (s.stream) (void)hipStreamSynchronize(s.stream);
         if (s.ev) (void)hipEventDestroy(s.ev);
         if (s.stream) (void)hipStreamDestroy(s.stream);
-        if (s.h_hdr) (void)hipHostFree(s.h_hdr);
+        if (s.h_buf) (void)hipHostFree(s.h_buf);
         if (s.h_out) (void)hipHostFree(s.h_out);
-        if (s.d_hdr) (void)dev_release(s.d_hdr);
+        if (s.d_buf) (void)dev_release(s.d_buf);
         if (s.d_out) (void)dev_release(s.d_out);
     }
     delete srv;
@@ -292,11 +304,12 @@ int tang_server_create(int device, const tang_server_cfg_t* cfg, tang_server_t**
         for (auto& s : srv->slots) {
             if (e == hipSuccess) e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
-            if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_hdr, c.max_batch * sizeof(tang_header_t), 0);
+            const size_t stage = ((size_t)c.max_batch + 1) * sizeof(tang_header_t);
+            if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_buf, stage, 0);
             if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_out, c.max_batch * sizeof(uint32_t), 0);
-            if (e == hipSuccess) e = dev_alloc(&s.d_hdr, c.max_batch * sizeof(tang_header_t));
+            if (e == hipSuccess) e = dev_alloc(&s.d_buf, stage);
             if (e == hipSuccess) e = dev_alloc(&s.d_out, c.max_batch * sizeof(uint32_t));
-            if (e == hipSuccess) e = hipMemset(s.d_hdr, 0, c.max_batch * sizeof(tang_header_t));
+            if (e == hipSuccess) e = hipMemset(s.d_buf, 0, stage);
         }
         if (e != hipSuccess) {
             free_server(srv);

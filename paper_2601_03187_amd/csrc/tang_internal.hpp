@@ -43,11 +43,25 @@ constexpr uint32_t kMaxBucketLen = (1u << kTlShift) - 1u;
 constexpr uint32_t kSplit = 0x80000000u;
 constexpr uint32_t kSplitAt = 16;
 enum : uint32_t { kSubDp = 1, kSubSp = 2, kSubProto = 3, kSubRest = 4 };
-constexpr uint32_t kKindShift = 8;   // tuples < 256; tuple | kind << 8 fits the slot's 12 bits
+constexpr uint32_t kKindShift = 9;   // tuples < 512; tuple | kind << 9 fits the slot's 12 bits
 
-// Conflict masks: one word per rule (in the record) for rulesets of at most 32 tuples,
-// kMaskWords words per rule (a side array indexed like the records) up to 256 tuples.
+// Conflict masks: one word per rule (in the record) for rulesets of at most 32 tuples;
+// wider ones keep a side array indexed like the records, kMaskWords words per rule for
+// at most 256 tuples and kMaxWords for more (up to TANG_MAX_TUPLES).
 constexpr int kMaskWords = 8;
+constexpr int kMaxWords = TANG_MAX_TUPLES / 32;
+// Mask words for a tuple count, and the tuple limit of a mask width.
+inline uint32_t words_for(size_t tuples) {
+    return tuples <= 32 ? 1u : tuples <= 32u * kMaskWords ? (uint32_t)kMaskWords : (uint32_t)kMaxWords;
+}
+inline size_t tuple_limit(uint32_t nw) { return 32u * (size_t)nw; }
+// Candidate tuples in the predictor's output word: one byte each up to 256 tuples (at
+// most 4 candidates), 16 bits each above (at most 2).
+__host__ __device__ inline uint32_t cand_bits(int n_tuples) { return n_tuples > 256 ? 16u : 8u; }
+inline int max_topk(int n_tuples) {
+    const int k = n_tuples > 256 ? 2 : TANG_MAX_TOPK;
+    return k < n_tuples ? k : n_tuples;
+}
 
 // Rec (32 B): one rule as the bucket scan reads it, hot half first. The scan reads the
 // first 16 bytes of each record (one load): ports, priority and the protocol/length
@@ -96,20 +110,20 @@ constexpr int kMaxGroups = 64;
 constexpr uint32_t kNoGroup = 0xFFu;
 struct TupleTable {
     TupleDev t[TANG_MAX_TUPLES];
-    uint8_t order[TANG_MAX_TUPLES];  // tuple indices by ascending best key
+    uint16_t order[TANG_MAX_TUPLES]; // tuple indices by ascending best key
     uint32_t rank_prio[TANG_MAX_TUPLES], rank_id[TANG_MAX_TUPLES];  // best keys in that order
     // prefix[k]: the k tuples of lowest best key, as mask words
-    uint32_t prefix[TANG_MAX_TUPLES + 1][kMaskWords];
+    uint32_t prefix[TANG_MAX_TUPLES + 1][kMaxWords];
     uint32_t n;                       // number of tuples
-    uint32_t all_mask[kMaskWords];    // bits of all tuples
+    uint32_t all_mask[kMaxWords];     // bits of all tuples
     uint32_t slot_mask;               // slots - 1
     uint32_t filter_mask;             // filter blocks - 1
-    uint32_t nw;                      // mask words of this ruleset (1 or kMaskWords)
+    uint32_t nw;                      // mask words of this ruleset (1, kMaskWords or kMaxWords)
     uint8_t gid[TANG_MAX_TUPLES];     // filter group of each tuple (kNoGroup: none)
     uint32_t ngroups;
     uint32_t gkey[kMaxGroups];        // side (bit 6: 1 = DIP) | prefix length (bits 0-5)
-    uint32_t gmask[kMaxGroups][kMaskWords];  // tuples of each group
-    uint32_t nogroup[kMaskWords];     // tuples without a group (always pass)
+    uint32_t gmask[kMaxGroups][kMaxWords];  // tuples of each group
+    uint32_t nogroup[kMaxWords];      // tuples without a group (always pass)
 };
 
 // Key hash: two chained MurmurHash3 32-bit finalisers (fmix32, Appleby, public domain),
@@ -249,13 +263,13 @@ struct tang_ruleset_s {
     std::vector<tang::Slot> slots;                 // host mirror of the slot table
     std::vector<uint32_t> filter;                  // host mirror of the bucket filter (2 words per block)
     uint32_t rec_used = 0, rec_cap = 0;
-    uint32_t nw = 1;   // conflict-mask words per rule (fixed at build: 1, or kMaskWords)
+    uint32_t nw = 1;   // conflict-mask words per rule (fixed at build: words_for(tuples))
 
     // device state
     tang::Slot* d_slots = nullptr;
     uint32_t* d_filter = nullptr;
     tang::Rec* d_recs = nullptr;
-    uint32_t* d_cmask = nullptr;   // nw > 1: kMaskWords words per record position
+    uint32_t* d_cmask = nullptr;   // nw > 1: nw words per record position
     tang::TupleTable* d_tt = nullptr;
     tang::StatsDev* d_stats = nullptr;
     hipStream_t upd_stream = nullptr;
@@ -306,8 +320,12 @@ inline hipError_t dev_alloc(T** p, size_t bytes) {
 }
 
 // Kernel launchers (k_classify.hip, k_build.hip, k_mlp.hip).
+// d_live (optional): a device word holding the live header count, read by the kernels at
+// their start; lanes and workgroups past min(n, *d_live) do nothing. A launch recorded
+// once into a graph for n headers then serves any smaller batch without padding.
 hipError_t launch_classify(const tang_ruleset_t* rs, const tang_header_t* d_hdr,
-                           uint32_t* d_out, size_t n, int kcand, hipStream_t s, bool stats);
+                           uint32_t* d_out, size_t n, int kcand, hipStream_t s, bool stats,
+                           const uint32_t* d_live = nullptr);
 hipError_t launch_conflict_build(const BoxDev* d_boxes, size_t n, Rec* d_recs, uint32_t* d_cmask,
                                  uint32_t nw, const uint32_t* all_mask,
                                  hipStream_t s);
@@ -317,8 +335,8 @@ hipError_t launch_move_records(Rec* d_recs, const Rec* d_src_recs, const uint32_
                                const uint32_t* d_dst, uint32_t n, Rec* d_stage, hipStream_t s);
 // nw > 1: the mask rows move with their records (the same src / dst lists; new sources
 // get zero rows), through a stage of n rows.
-hipError_t launch_move_masks(uint32_t* d_cmask, const uint32_t* d_src, const uint32_t* d_dst,
-                             uint32_t n, uint32_t* d_stage, hipStream_t s);
+hipError_t launch_move_masks(uint32_t* d_cmask, uint32_t nw, const uint32_t* d_src,
+                             const uint32_t* d_dst, uint32_t n, uint32_t* d_stage, hipStream_t s);
 hipError_t launch_scatter_slots(Slot* d_slots, const uint32_t* d_idx, const Slot* d_val,
                                 uint32_t n, hipStream_t s);
 // Batches of at least two chunks of this many headers, with a BF16 or FP8 model and no
@@ -328,20 +346,22 @@ constexpr size_t kPipeChunk = (size_t)1 << 21;
 constexpr size_t kNoAllocMaxHeaders = (size_t)1 << 18;
 // tang_classify's body; allow_chunks = false keeps every launch on stream s (for callers
 // that capture the launches into a graph).
+// d_live: as for launch_classify (with a plain MLP or no model; not with stats).
 int classify_async(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint32_t* d_rule_id, size_t n,
-                   hipStream_t s, tang_stats_t* stats, bool allow_chunks);
+                   hipStream_t s, tang_stats_t* stats, bool allow_chunks,
+                   const uint32_t* d_live = nullptr);
 // beside_search: the launch overlaps a search on another stream (the chunked classify),
 // so the predictor leaves room on every SIMD for search waves.
 hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
-                      uint32_t* d_cand_packed, float* d_logits, uint8_t* d_cand8,
-                      hipStream_t s, bool beside_search = false);
+                      uint32_t* d_cand_packed, float* d_logits, uint16_t* d_cand16,
+                      hipStream_t s, bool beside_search = false, const uint32_t* d_live = nullptr);
 int search_host(const tang_ruleset_t* rs, const tang_header_t* hdr, const uint32_t* cand,
                 uint32_t* out, size_t n, uint32_t kcand, uint32_t threads, bool exact,
                 tang_stats_t* stats);
 int resnet_prepare(tang_ruleset_t* rs, const tang_resnet_desc_t* d, const float* const* W,
                    const float* const* b, tang_precision_t p);
 hipError_t launch_resnet(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size_t n,
-                         uint32_t* cand, float* logits, uint8_t* cand8, hipStream_t s);
+                         uint32_t* cand, float* logits, uint16_t* cand16, hipStream_t s);
 int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* const* W,
                   const float* const* b, tang_precision_t p, const float* act_scales);
 void model_free(ModelDev& m);

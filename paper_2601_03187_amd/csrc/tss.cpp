@@ -176,10 +176,10 @@ TupleTable make_tuple_table(const tang_ruleset_t* rs) {
     std::stable_sort(ord.begin(), ord.end(),
                      [&](uint32_t a, uint32_t b) { return rs->tuple_best[a] < rs->tuple_best[b]; });
     for (uint32_t i = 0; i < n; ++i) {
-        tt.order[i] = (uint8_t)ord[i];
+        tt.order[i] = (uint16_t)ord[i];
         tt.rank_prio[i] = (uint32_t)(rs->tuple_best[ord[i]] >> 32);
         tt.rank_id[i] = (uint32_t)rs->tuple_best[ord[i]];
-        for (int w = 0; w < kMaskWords; ++w) tt.prefix[i + 1][w] = tt.prefix[i][w];
+        for (int w = 0; w < kMaxWords; ++w) tt.prefix[i + 1][w] = tt.prefix[i][w];
         tt.prefix[i + 1][ord[i] >> 5] |= 1u << (ord[i] & 31u);
     }
     tt.n = n;
@@ -233,13 +233,14 @@ int build_host(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
         while (t < rs->sigs.size() && rs->sigs[t] != sig) ++t;
         if (t == rs->sigs.size()) {
             if (rs->sigs.size() == TANG_MAX_TUPLES)
-                return fail(TANG_EINVAL, "more than 256 distinct (sip_len, dip_len) signatures");
+                return fail(TANG_EINVAL, "more than " + std::to_string(TANG_MAX_TUPLES) +
+                                             " distinct (sip_len, dip_len) signatures");
             rs->sigs.push_back(sig);
             rs->tuple_best.push_back(key_of(hr.r));
         }
         hr.tuple = (uint32_t)t;
     }
-    rs->nw = rs->sigs.size() <= 32 ? 1u : (uint32_t)kMaskWords;
+    rs->nw = words_for(rs->sigs.size());
 
     // Buckets keyed by (tuple, masked SIP, masked DIP), members in key order.
     for (uint32_t h : order) {
@@ -280,8 +281,8 @@ int upload_all(tang_ruleset_t* rs) {
                        hipMemcpyHostToDevice));
     TANG_HIP(dev_alloc(&rs->d_recs, (size_t)rs->rec_cap * sizeof(Rec)));
     if (rs->nw > 1) {
-        TANG_HIP(dev_alloc(&rs->d_cmask, (size_t)rs->rec_cap * kMaskWords * sizeof(uint32_t)));
-        TANG_HIP(hipMemset(rs->d_cmask, 0, (size_t)rs->rec_cap * kMaskWords * sizeof(uint32_t)));
+        TANG_HIP(dev_alloc(&rs->d_cmask, (size_t)rs->rec_cap * rs->nw * sizeof(uint32_t)));
+        TANG_HIP(hipMemset(rs->d_cmask, 0, (size_t)rs->rec_cap * rs->nw * sizeof(uint32_t)));
     }
     TANG_HIP(dev_alloc(&rs->d_tt, sizeof(TupleTable)));
     TANG_HIP(dev_alloc(&rs->d_stats, kStatCopies * sizeof(StatsDev)));
@@ -370,7 +371,7 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
                                 hipMemcpyHostToDevice, s));
         if (rs->nw > 1) {
             uint32_t* nmask = nullptr;
-            const size_t row = kMaskWords * sizeof(uint32_t);
+            const size_t row = rs->nw * sizeof(uint32_t);
             TANG_HIP(dev_alloc(&nmask, (size_t)ncap * row));
             TANG_HIP(hipMemsetAsync(nmask, 0, (size_t)ncap * row, s));
             TANG_HIP(hipMemcpyAsync(nmask, rs->d_cmask, (size_t)rs->rec_used * row,
@@ -448,10 +449,10 @@ int flush(tang_ruleset_t* rs, const std::vector<uint32_t>& dirty, const std::vec
                                     (const uint32_t*)d_dst, (uint32_t)dst.size(), (Rec*)d_stage, s);
         if (e == hipSuccess && rs->nw > 1) {
             void* d_mstage = nullptr;
-            e = dev_alloc(&d_mstage, dst.size() * kMaskWords * sizeof(uint32_t));
+            e = dev_alloc(&d_mstage, dst.size() * rs->nw * sizeof(uint32_t));
             if (e == hipSuccess) {
                 tmp.push_back(d_mstage);
-                e = launch_move_masks(rs->d_cmask, (const uint32_t*)d_src, (const uint32_t*)d_dst,
+                e = launch_move_masks(rs->d_cmask, rs->nw, (const uint32_t*)d_src, (const uint32_t*)d_dst,
                                       (uint32_t)dst.size(), (uint32_t*)d_mstage, s);
             }
         }
@@ -550,11 +551,10 @@ int apply_insert(tang_ruleset_t* rs, const tang_rule_t* rules, size_t n) {
             return fail(TANG_EEXIST, "rule id " + std::to_string(rules[i].id) + " is live or repeated");
         int t = choose_tuple(sigs, rules[i].sip_len, rules[i].dip_len);
         if (t < 0) {
-            if (sigs.size() == (rs->nw == 1 ? 32u : (size_t)TANG_MAX_TUPLES))
-                return fail(TANG_EINVAL, rs->nw == 1
-                                             ? "insert would need a 33rd tuple (the ruleset was built "
-                                               "with one conflict-mask word)"
-                                             : "insert would need a tuple beyond 256");
+            if (sigs.size() == tuple_limit(rs->nw))
+                return fail(TANG_EINVAL, "insert would need tuple " + std::to_string(sigs.size() + 1) +
+                                             " (the ruleset was built with " + std::to_string(rs->nw) +
+                                             " conflict-mask words per rule)");
             t = (int)sigs.size();
             sigs.emplace_back(rules[i].sip_len, rules[i].dip_len);
         }

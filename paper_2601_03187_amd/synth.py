@@ -50,6 +50,10 @@ IP_LEN_P = np.array([0.40, 0.20, 0.15, 0.10, 0.15])
 # a wide tuple space: 12 lengths per field, uniform -> 144 (SIP, DIP) signatures, in
 # the range of the paper's rulesets (31-391 tuples)
 WIDE_IP_LENS = np.array([32, 30, 28, 26, 24, 22, 20, 18, 16, 12, 8, 0], dtype=np.int64)
+# every prefix length: the SIP length uniform over 0..32 and the DIP length within
+# ALL_LEN_SPREAD of it (clipped to 0..32) -> 387 (SIP, DIP) signatures, near the paper's
+# largest ruleset (391 tuples)
+ALL_LEN_SPREAD = 6
 MIX_IP_LENS = np.array([16, 8, 0], dtype=np.int64)
 MIX_IP_LEN_P = np.array([0.25, 0.25, 0.50])
 PORT_P = np.array([0.60, 0.25, 0.15])            # wildcard, exact, range
@@ -82,14 +86,18 @@ def _draw_ports(rng, n, probs):
 
 
 def make_rules(n: int, seed: int, ordering: str = "specificity", mix: float = 0.0,
-               wide: bool = False) -> np.ndarray:
+               wide: bool = False, all_lengths: bool = False) -> np.ndarray:
     """Draw `n` 5-field rules. Returns a RULE_DTYPE array with priority = id = index.
-    wide: IP prefix lengths uniform over WIDE_IP_LENS (a tuple space of ~144 tuples)."""
+    wide: IP prefix lengths uniform over WIDE_IP_LENS (a tuple space of ~144 tuples).
+    all_lengths: every prefix length 0..32 (see ALL_LEN_SPREAD; ~387 tuples)."""
     if ordering not in ("specificity", "literal"):
         raise ValueError(ordering)
     rng = _rng(seed)
     heavy = rng.random(n) < mix
-    if wide:
+    if all_lengths:
+        sl = rng.integers(0, 33, size=n)
+        dl = np.clip(sl + rng.integers(-ALL_LEN_SPREAD, ALL_LEN_SPREAD + 1, size=n), 0, 32)
+    elif wide:
         sl = rng.choice(WIDE_IP_LENS, size=n)
         dl = rng.choice(WIDE_IP_LENS, size=n)
     else:
@@ -248,12 +256,16 @@ CONFIGS = {
     "c4_512k_updates": dict(n_rules=524_288, n_pkts=1_000_000, frac_in=0.80, zipf=None,
                             mix=0.0, hidden=256, seed=404, rounds=100, per_round=100),
     "c5_serving": dict(sizes=(10_000, 100_000, 524_288), frac_in=0.80, hidden=256, seed=505),
-    # the paper's dynamic experiment (Sec. 7.4) scaled to one GPU: windows of deletes and
-    # inserts with a SIP prefix length the tuple set does not have (a drifting
-    # distribution; one new length keeps a rebuilt tuple space within 32 tuples)
     # a wide tuple space (144 tuples): 512k rules, 16M Zipf headers
     "c7_wide": dict(n_rules=524_288, n_pkts=16_777_216, frac_in=1.0, zipf=1.0, mix=0.0,
                     hidden=256, seed=707),
+    # every prefix length 0..32 (387 tuples, the size of the paper's largest tuple
+    # spaces): 512k rules, 16M Zipf headers
+    "c8_all_lengths": dict(n_rules=524_288, n_pkts=16_777_216, frac_in=1.0, zipf=1.0,
+                           mix=0.0, hidden=256, seed=808),
+    # the paper's dynamic experiment (Sec. 7.4) scaled to one GPU: windows of deletes and
+    # inserts with a SIP prefix length the tuple set does not have (a drifting
+    # distribution; one new length keeps a rebuilt tuple space within 32 tuples)
     "c6_drift": dict(n_rules=65_536, windows=10, per_window=2_000, n_pkts=1_000_000,
                      frac_in=0.80, hidden=256, seed=606, sip_lengths=(4,)),
 }

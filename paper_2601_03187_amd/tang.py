@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtang.so")
 
 TANG_NO_MATCH = 0xFFFFFFFF
 TANG_HOST_ONLY = -1
-TANG_MAX_TUPLES = 256
+TANG_MAX_TUPLES = 512
 TANG_NOALLOC_MAX_HEADERS = 262144
 TANG_FP32, TANG_BF16, TANG_FP8 = 0, 1, 2
 PRECISIONS = {"fp32": TANG_FP32, "bf16": TANG_BF16, "fp8": TANG_FP8}
@@ -202,9 +202,10 @@ def tang_ruleset_rule_tuple(rs: int, rule_id: int) -> int:
 
 
 def tang_ruleset_conflict_mask(rs: int, rule_id: int) -> int:
-    """The whole conflict mask as a Python int (bit t = tuple t, up to 256 tuples)."""
-    words = (ctypes.c_uint32 * 8)()
-    _check(_lib.tang_ruleset_conflict_mask_words(rs, rule_id, ctypes.cast(words, _P), 8))
+    """The whole conflict mask as a Python int (bit t = tuple t, up to TANG_MAX_TUPLES)."""
+    nw = TANG_MAX_TUPLES // 32
+    words = (ctypes.c_uint32 * nw)()
+    _check(_lib.tang_ruleset_conflict_mask_words(rs, rule_id, ctypes.cast(words, _P), nw))
     return sum(int(w) << (32 * i) for i, w in enumerate(words))
 
 
@@ -348,7 +349,7 @@ def tang_mlp_forward(rs: int, d_hdr, n: int, d_logits=None, d_cand=None, stream=
     k = _model_topk.get(rs, 1)
     _check(_lib.tang_mlp_forward(rs, _dbuf(d_hdr, 16 * n, "d_hdr"), n,
                                  _dbuf(d_logits, 4 * n * C, "d_logits"),
-                                 _dbuf(d_cand, n * k, "d_cand"), _stream(stream)))
+                                 _dbuf(d_cand, 2 * n * k, "d_cand"), _stream(stream)))
 
 
 # --- updates ----------------------------------------------------------------------------

@@ -32,10 +32,10 @@ def mlp_dev(rs, hdr: np.ndarray, n_out: int, topk: int = 1):
     n = len(hdr)
     d_hdr = to_dev(hdr)
     logits = torch.full((n * n_out,), float("nan"), dtype=torch.float32, device="cuda")
-    cand = torch.full((n * topk,), 255, dtype=torch.uint8, device="cuda")
+    cand = torch.full((n * topk,), -1, dtype=torch.int16, device="cuda")
     T.tang_mlp_forward(rs, d_hdr, n, logits, cand, torch.cuda.current_stream())
     torch.cuda.synchronize()
-    return logits.cpu().numpy().reshape(n, n_out), cand.cpu().numpy().reshape(n, topk)
+    return logits.cpu().numpy().reshape(n, n_out), cand.cpu().numpy().view(np.uint16).reshape(n, topk)
 
 
 def keys_of(rules: np.ndarray, ids: np.ndarray) -> np.ndarray:

@@ -1,9 +1,10 @@
-"""The largest tuple space a ruleset holds: 256 tuples, every pair of 16 prefix lengths
-(Sec. 4.3's (SIP length, DIP length) signatures). All eight conflict-mask words are in use,
-tuple 255 is a valid candidate in the packed top-k word, the output layer has 256 classes
-(eight 32-class blocks under the running top-k), restricted insertion (Sec. 5.2.1) keeps
-the count at 256, and an insert that would need a 257th tuple fails without changing the
-answers. Every answer equals the oracle's linear scan."""
+"""The largest tuple space of the eight-word mask width: 256 tuples, every pair of 16
+prefix lengths (Sec. 4.3's (SIP length, DIP length) signatures). All eight conflict-mask
+words are in use, tuple 255 is a valid candidate in the packed top-k word (one byte per
+candidate), the output layer has 256 classes (eight 32-class blocks under the running
+top-k), restricted insertion (Sec. 5.2.1) keeps the count at 256, and an insert that would
+need a 257th tuple fails without changing the answers (the width is fixed at build). Every
+answer equals the oracle's linear scan."""
 import numpy as np
 import pytest
 
@@ -41,7 +42,7 @@ def test_max_tuples_conflict_masks_equal_bruteforce():
     want = orc.conflict_masks(rules, rt)
     rs = T.tang_ruleset_create(0, rules)
     try:
-        assert T.tang_ruleset_num_tuples(rs) == T.TANG_MAX_TUPLES
+        assert T.tang_ruleset_num_tuples(rs) == 256
         assert max(int(w) for w in want) >> 224
         for k in range(len(rules)):
             assert T.tang_ruleset_rule_tuple(rs, int(rules[k]["id"])) == rt[k]

@@ -33,14 +33,14 @@ def _hidden_amax(X, Ws, bs):
     return out
 
 
-@pytest.mark.parametrize("wide", [False, True])
+@pytest.mark.parametrize("wide", [False, True, "all"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("hidden", [128, 256])
 def test_logits_and_candidates_vs_oracle(prec, hidden, wide):
-    """wide: 144 tuples, so the output layer runs over several 64-class blocks with a
-    running top-k."""
+    """wide: 144 tuples, so the output layer runs over several 32-class blocks with a
+    running top-k; "all": every prefix length, 387 tuples (16-bit candidates)."""
     torch_cuda()
-    rules = synth.make_rules(3000, seed=41, wide=wide)
+    rules = synth.make_rules(3000, seed=41, wide=wide is True, all_lengths=wide == "all")
     hdr = synth.make_packets(rules, 3001, seed=42, frac_in=0.7)  # ragged: not a tile multiple
     rs = T.tang_ruleset_create(0, rules)
     try:
@@ -63,6 +63,10 @@ def test_logits_and_candidates_vs_oracle(prec, hidden, wide):
         # candidates: valid, distinct, and equal to the oracle's where the margin is clear
         assert (cand < C).all() and (cand[:, 0] != cand[:, 1]).all()
         srt = np.sort(want, axis=1)
+        # on every row the first candidate is a maximum up to the logits' error: its oracle
+        # score is within twice the loose bound of the oracle's best
+        rows = np.arange(len(hdr))
+        assert (want[rows, cand[:, 0]] >= srt[:, -1] - 2 * loose.max(axis=1)).all()
         margin = srt[:, -1] - srt[:, -2]
         rows_ok = (err <= tight).all(axis=1) & (margin > 2 * tight.max(axis=1))
         top = orc.topk(want, 2)

@@ -288,7 +288,7 @@ def test_binding_refuses_buffers_shorter_than_n():
         assert np.array_equal(d_out.cpu().numpy().view(np.uint32), orc.classify(rules, hdr))
         Ws, bs = train.random_weights(T.tang_ruleset_num_tuples(rs), 128, seed=1)
         _load(rs, Ws, bs, "bf16", topk=2)
-        cand = torch.empty(150, dtype=torch.uint8, device="cuda")   # needs 100 x 2
+        cand = torch.empty(150, dtype=torch.int16, device="cuda")   # needs 100 x 2
         with pytest.raises(ValueError):
             T.tang_mlp_forward(rs, d_hdr, 100, None, cand, s)
     finally:
