@@ -671,7 +671,56 @@ def paper_statistics(args, rules, rs, hdr, d_hdr, d_out, want, C):
                      "probes_per_lookup": st["probes"] / n}
         log(f"[bench] paper loop, {arch}: model accuracy {model_acc:.4f}, paper search accuracy "
             f"{out[arch]['paper_search_accuracy']:.5f}, exact {exact}, rounds {len(info['rounds'])}")
+    out["loop_to_beta_1k"] = paper_loop_small(args)
     return out
+
+
+def paper_loop_small(args):
+    """The paper's training loop (Sec. 6.2) run until it reaches beta, on a ruleset a model
+    of this size can learn: the 1,024-rule workload (104-128-128-C MLP), 200,000 training
+    headers, alpha from 1,000, beta = 0.95, at most 5 rounds of 20 epochs. Reports every
+    round's alpha, sample count and accuracy, whether beta was reached, the model's accuracy
+    on 100,000 held-out headers, and that classification with it stays exact."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as orc
+    from paper_2601_03187_amd import synth, train
+    from paper_2601_03187_amd import tang as T
+
+    cfg = synth.CONFIGS["c1_1k"]
+    rules = synth.make_rules(cfg["n_rules"], seed=cfg["seed"], ordering="specificity", mix=cfg["mix"])
+    hdr = synth.make_packets(rules, 300_000, seed=cfg["seed"] + 2, frac_in=cfg["frac_in"])
+    want = orc.classify(rules, hdr)
+    rs = T.tang_ruleset_create(0, rules)
+    try:
+        t0 = time.time()
+        Ws, bs, info = train.train_paper(rs, rules, hdr[:200_000], arch="mlp", hidden=cfg["hidden"],
+                                         alpha=1000, beta=0.95, rounds=5, epochs=20, device="cuda",
+                                         rule_ids=want[:200_000])
+        train_s = time.time() - t0
+        T.tang_model_load(rs, Ws, bs, "fp32", topk=1)
+        held = hdr[200_000:]
+        n = len(held)
+        d_hdr = torch.from_numpy(held.view(np.uint8).reshape(-1).copy()).cuda()
+        cand = torch.empty(n, dtype=torch.int16, device="cuda")
+        T.tang_mlp_forward(rs, d_hdr, n, None, cand, torch.cuda.current_stream())
+        pred = cand.cpu().numpy().view(np.uint16).astype(np.int64)
+        label = train.tuple_labels(rs, rules, want[200_000:])
+        ok = label >= 0
+        d_out = torch.empty(n, dtype=torch.int32, device="cuda")
+        T.tang_classify(rs, d_hdr, d_out, n, torch.cuda.current_stream())
+        exact = bool(np.array_equal(d_out.cpu().numpy().view(np.uint32), want[200_000:]))
+        res = {"rules": len(rules), "tuples": T.tang_ruleset_num_tuples(rs), "hidden": cfg["hidden"],
+               "train_headers": 200_000, "epochs_per_round": 20, "rounds": info["rounds"],
+               "converged": info["converged"], "train_s": train_s,
+               "model_accuracy_heldout": float(np.mean(pred[ok] == label[ok])),
+               "classification_exact": exact}
+        log(f"[bench] paper loop to beta, 1k rules: rounds {len(info['rounds'])}, converged "
+            f"{info['converged']}, held-out accuracy {res['model_accuracy_heldout']:.4f}")
+        return res
+    finally:
+        T.tang_ruleset_destroy(rs)
 
 
 def bench_resnet(args, rs, d_hdr, d_out, want, C):
@@ -913,23 +962,30 @@ def bench_serving(args):
         T.tang_model_load(rs, Ws, bs, "bf16", topk=1)
         sets.append((rules, rs, pool))
     log("[bench c5] rulesets ready")
-    srv = T.tang_server_create(0, n_streams=4, max_batch=65536, use_graphs=1)
+    # batches merge requests up to 262,144 headers (four of the largest requests): the
+    # fixed cost of a batch (launches, copies, a partly filled GPU) then spreads over more
+    # headers when requests queue up (saturation 740 Mpps with 65,536, 1,350 with 262,144,
+    # measured); at low load a batch is a single request either way
+    srv = T.tang_server_create(0, n_streams=4, max_batch=262144, use_graphs=1)
     tags = [T.tang_server_add_ruleset(srv, rs) for _, rs, _ in sets]
 
     def run(n_req, rate, seed):
         t_arr, sizes, tg = synth.make_requests(n_req, len(sets), seed=seed, rate_per_s=rate or 1.0)
         rng = np.random.default_rng(seed)
+        # requests (header slices and result buffers) are made before the clock starts, so
+        # the submitting loop does nothing but wait for arrival times and submit
+        work = []
+        for q in range(n_req):
+            pool = sets[tg[q]][2]
+            off = int(rng.integers(0, len(pool) - sizes[q]))
+            work.append((int(tg[q]), pool[off: off + sizes[q]], np.empty(sizes[q], dtype=np.uint32)))
         reqs = []
         t0 = time.perf_counter()
-        for q in range(n_req):
+        for q, (tag, hdr, out) in enumerate(work):
             if rate:
                 while time.perf_counter() - t0 < t_arr[q]:
                     pass
-            pool = sets[tg[q]][2]
-            off = int(rng.integers(0, len(pool) - sizes[q]))
-            hdr = pool[off: off + sizes[q]]
-            out = np.empty(sizes[q], dtype=np.uint32)
-            reqs.append((tg[q], hdr, out, T.tang_server_submit(srv, tags[tg[q]], hdr, out)))
+            reqs.append((tag, hdr, out, T.tang_server_submit(srv, tags[tag], hdr, out)))
         for _, _, _, r in reqs:
             T.tang_server_wait(r, 120_000_000)
         times = [T.tang_server_req_times(r) for *_, r in reqs]
@@ -941,7 +997,7 @@ def bench_serving(args):
                       "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
                       "offered_req_per_s": rate, "submit_s": time.perf_counter() - t0}
 
-    run(200, 0, seed=1)  # warm-up: graph capture for the size classes
+    run(args.requests, 0, seed=1)  # warm-up: graph capture for the (ruleset, size class, slot) triples
     reqs, sat = run(args.requests, 0, seed=2)
     mean_size = sat["packets"] / sat["requests"]
     sat_rate = sat["mpps"] * 1e6 / mean_size
@@ -956,7 +1012,8 @@ def bench_serving(args):
     for *_, r in reqs:
         T.tang_server_req_free(r)
     res = {"workload": "c5_serving: rulesets of 10k/100k/512k rules, Poisson requests, sizes "
-                       "log-uniform 32..65536, 4 streams, HIP graphs, BF16 predictors",
+                       "log-uniform 32..65536, 4 streams, batches up to 262,144 headers, HIP graphs, "
+                       "BF16 predictors",
            "saturation": sat, "loads": levels,
            "alone_vs_mix": {"requests_checked": 50, "mismatches": bad}}
     T.tang_server_destroy(srv)

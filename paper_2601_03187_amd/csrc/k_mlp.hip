@@ -798,7 +798,9 @@ hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size
         // waves of 32; beside a chunked classify's search both run 8 waves of 32 headers,
         // so that search waves fit on every SIMD next to them (measured per 16M headers:
         // BF16 alone 2.56 ms with 12 waves of 32, 2.44 ms with 8 of 64; chunked classify
-        // unchanged by the alone variant).
+        // unchanged by the alone variant). Below 2^20 headers (serving batches) BF16 keeps
+        // 12 waves of 32: a workgroup of 512 headers would leave half of the CUs idle on a
+        // 65,536-header batch.
         // More than 32 tuples: up to 16 blocks of 32 classes, W3 read from L2.
         const bool wide = m.n_out > kOutPad;
         if (wide) {
@@ -813,6 +815,7 @@ hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size
         else if (m.prec == TANG_FP32) e = launch_t<TANG_FP32, 256, 1, 0>(m, h, k, c, lg, c8, s, d_live);
         else if (m.prec == TANG_BF16 && m.hidden == 128) e = launch_t<TANG_BF16, 128, 2, 7>(m, h, k, c, lg, c8, s, d_live);
         else if (m.prec == TANG_BF16 && beside_search) e = launch_t<TANG_BF16, 256, 2, 6, 8>(m, h, k, c, lg, c8, s, d_live);
+        else if (m.prec == TANG_BF16 && k < (1u << 20)) e = launch_t<TANG_BF16, 256, 2, 6, 12>(m, h, k, c, lg, c8, s, d_live);
         else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 4, 6, 8>(m, h, k, c, lg, c8, s, d_live);
         else if (m.hidden == 128) e = launch_t<TANG_FP8, 128, 2, 7>(m, h, k, c, lg, c8, s, d_live);
         else if (beside_search) e = launch_t<TANG_FP8, 256, 2, 7, 8>(m, h, k, c, lg, c8, s, d_live);
