@@ -432,7 +432,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                     }
                 }
             }
-            __builtin_amdgcn_sched_barrier(0);
+            // FP8 groups are left to the scheduler, which then overlaps one group's scale /
+            // clamp / conversion epilogue with the next group's MFMAs (chunked classify
+            // 3.17 -> 3.07 ms per 16M headers); for BF16 the same freedom was slower
+            // (predictor 2.48 -> 2.60 ms)
+            if constexpr (PREC != TANG_FP8) __builtin_amdgcn_sched_barrier(0);
         }
         // layer 3: H -> C in blocks of 32 classes (two 16-row tiles). With one block each
         // lane's 8 scores go straight to the top-k; with more, each lane keeps a running
@@ -794,8 +798,9 @@ hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size
         // LDSM: which layers' fragments sit in LDS (bit l = layer l) -- 160 KB per CU.
         // FP32 reads its input layer's BF16 planes from L2 (bit 0 unused).
         // At H = 256 the predictor alone runs BF16 as 8 waves of 64 headers (NT = 4: each
-        // weight fragment read from LDS serves four header tiles; 254 VGPRs) and FP8 as 12
-        // waves of 32; beside a chunked classify's search both run 8 waves of 32 headers,
+        // weight fragment read from LDS serves four header tiles; 254 VGPRs) and FP8 as 16
+        // waves of 32 (its 126 VGPRs allow four per SIMD: 1.81 -> 1.71 ms against 12
+        // waves); beside a chunked classify's search both run 8 waves of 32 headers,
         // so that search waves fit on every SIMD next to them (measured per 16M headers:
         // BF16 alone 2.56 ms with 12 waves of 32, 2.44 ms with 8 of 64; chunked classify
         // unchanged by the alone variant). Below 2^20 headers (serving batches) BF16 keeps
@@ -819,7 +824,7 @@ hipError_t launch_mlp(const tang_ruleset_t* rs, const tang_header_t* d_hdr, size
         else if (m.prec == TANG_BF16) e = launch_t<TANG_BF16, 256, 4, 6, 8>(m, h, k, c, lg, c8, s, d_live);
         else if (m.hidden == 128) e = launch_t<TANG_FP8, 128, 2, 7>(m, h, k, c, lg, c8, s, d_live);
         else if (beside_search) e = launch_t<TANG_FP8, 256, 2, 7, 8>(m, h, k, c, lg, c8, s, d_live);
-        else e = launch_t<TANG_FP8, 256, 2, 7, 12>(m, h, k, c, lg, c8, s, d_live);
+        else e = launch_t<TANG_FP8, 256, 2, 7, 16>(m, h, k, c, lg, c8, s, d_live);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
