@@ -997,7 +997,9 @@ def bench_serving(args):
                       "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
                       "offered_req_per_s": rate, "submit_s": time.perf_counter() - t0}
 
-    run(args.requests, 0, seed=1)  # warm-up: graph capture for the (ruleset, size class, slot) triples
+    run(args.requests, 0, seed=1)  # warm-up
+    # idle time: the loop records the graphs of every (ruleset, size class, slot) then
+    time.sleep(2.0)
     reqs, sat = run(args.requests, 0, seed=2)
     mean_size = sat["packets"] / sat["requests"]
     sat_rate = sat["mpps"] * 1e6 / mean_size

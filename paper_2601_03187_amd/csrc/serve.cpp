@@ -10,7 +10,10 @@
 // A graph is recorded for the largest batch of its size class (a power of two); the
 // batch's real header count travels in the same host-to-device copy as its headers (the
 // first 16 bytes of the slot's staging) and the kernels read it from there, so a batch
-// costs the work of its own headers, not of its class.
+// costs the work of its own headers, not of its class. While no request is pending and
+// no batch is on the GPU, the loop records the graphs of every size class on every slot
+// for rulesets added since (one at a time, yielding as soon as a request arrives), so
+// that requests seldom pay for a graph capture.
 // Requests that arrive while others are on the GPU are admitted as slots and budget
 // free up, so batches of different requests and rulesets overlap on the device.
 #include <chrono>
@@ -83,6 +86,7 @@ struct tang_server_s {
     bool stop = false;
     std::thread th;
     std::vector<char> warmed;
+    std::vector<char> prepared;   // every (size class, slot) graph recorded once
 
     void loop();
     void finish(StreamSlot& s, int status);
@@ -90,6 +94,7 @@ struct tang_server_s {
                std::vector<std::shared_ptr<ReqState>>& batch, size_t total);
     int graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uint32_t slot_idx,
                   hipGraphExec_t* out);
+    bool prepare(uint32_t tag, tang_ruleset_t* rs, bool warm);
 };
 
 using namespace tang;
@@ -173,6 +178,32 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, tang_ruleset_t* rs, bool wa
     return TANG_OK;
 }
 
+// Idle-time preparation of ruleset `tag`: the eager first call (kernel attributes) if
+// needed, then the graph of every size class on every slot. Returns false if it stopped
+// early because a request arrived (it resumes at the next idle moment; recorded graphs
+// stay). Failures are left to the request path, which reports them.
+bool tang_server_s::prepare(uint32_t tag, tang_ruleset_t* rs, bool warm) {
+    if (!cfg.use_graphs || rs->model.kind != 0) return true;
+    StreamSlot& s0 = slots[0];
+    if (!warm) {
+        if (classify_async(rs, s0.d_hdr(), s0.d_out, 32, s0.stream, nullptr, false) != TANG_OK) return true;
+        if (hipStreamSynchronize(s0.stream) != hipSuccess) return true;
+        std::lock_guard<std::mutex> g(mu);
+        warmed[tag] = 1;
+    }
+    for (uint32_t si = 0; si < slots.size(); ++si) {
+        for (uint64_t cls = 32; cls <= cfg.max_batch; cls <<= 1) {
+            {
+                std::lock_guard<std::mutex> g(mu);
+                if (!pending.empty() || stop) return false;
+            }
+            hipGraphExec_t exec = nullptr;
+            if (graph_for(tag, rs, (uint32_t)cls, si, &exec) != TANG_OK) return true;
+        }
+    }
+    return true;
+}
+
 void tang_server_s::finish(StreamSlot& s, int status) {
     const uint64_t t = now_ns();
     for (size_t k = 0; k < s.reqs.size(); ++k) {
@@ -254,8 +285,22 @@ void tang_server_s::loop() {
         if (!progressed) {
             any_busy = false;
             for (auto& s : slots) any_busy |= s.busy;
-            if (any_busy) cv.wait_for(lk, std::chrono::microseconds(20));
-            else if (pending.empty() && !stop) cv.wait_for(lk, std::chrono::milliseconds(50));
+            if (any_busy) {
+                cv.wait_for(lk, std::chrono::microseconds(20));
+            } else if (pending.empty() && !stop) {
+                uint32_t tag = 0;
+                while (tag < prepared.size() && prepared[tag]) ++tag;
+                if (tag < prepared.size()) {
+                    tang_ruleset_t* rs = rulesets[tag];
+                    const bool warm = warmed[tag] != 0;
+                    lk.unlock();
+                    const bool done = prepare(tag, rs, warm);
+                    lk.lock();
+                    if (done) prepared[tag] = 1;
+                } else {
+                    cv.wait_for(lk, std::chrono::milliseconds(50));
+                }
+            }
         }
     }
 }
@@ -332,6 +377,7 @@ int tang_server_add_ruleset(tang_server_t* srv, tang_ruleset_t* rs, uint32_t* ta
     *tag = (uint32_t)srv->rulesets.size();
     srv->rulesets.push_back(rs);
     srv->warmed.push_back(0);
+    srv->prepared.push_back(0);
     return TANG_OK;
 }
 
