@@ -756,10 +756,27 @@ def bench_resnet(args, rs, d_hdr, d_out, want, C):
     ok = bool(np.array_equal(d_out[:n].cpu().numpy().view(np.uint32), want[:n]))
     ms = time_classify(T, rs, d_hdr, d_out, n, reps)
     tflops = flop * n / (mlp_ms * 1e-3) / 1e12
+    # for scale: the vendor library's GEMM (torch -> hipBLASLt) on one residual layer's shape
+    # ([65,536 x 512] x [512 x 512], BF16), with the bias and without the residual / ReLU
+    m = 1 << 16
+    X = torch.randn(m, width, device="cuda", dtype=torch.bfloat16)
+    W = torch.randn(width, width, device="cuda", dtype=torch.bfloat16)
+    b = torch.randn(width, device="cuda", dtype=torch.bfloat16)
+    for _ in range(3):
+        torch.nn.functional.linear(X, W, b)
+    e0.record(s)
+    for _ in range(20):
+        torch.nn.functional.linear(X, W, b)
+    e1.record(s)
+    torch.cuda.synchronize()
+    lib_ms = e0.elapsed_time(e1) / 20
+    del X, W, b
     res = {"headers": n, "blocks": nb, "width": width, "precision": "bf16", "weights": "random",
            "flop_per_pkt": flop, "predict_ms": mlp_ms, "predict_mpps": n / mlp_ms / 1e3,
            "predict_tflops": tflops, "predict_frac_of_bf16_peak": tflops / PEAK_TFLOPS["bf16"],
-           "classify_ms": ms, "classify_mpps": n / ms / 1e3, "answers_equal_bf16_run": ok}
+           "classify_ms": ms, "classify_mpps": n / ms / 1e3, "answers_equal_bf16_run": ok,
+           "library_gemm_one_layer": {"shape": "65536 x 512 x 512, bf16, bias", "us": lib_ms * 1e3,
+                                      "tflops": 2 * m * width * width / (lib_ms * 1e-3) / 1e12}}
     log(f"[bench] residual predictor (6 x 512): predict {res['predict_mpps']:.0f} Mpps "
         f"({tflops:.0f} TFLOP/s), classify {res['classify_mpps']:.0f} Mpps, answers equal: {ok}")
     return res
