@@ -985,6 +985,8 @@ def bench_serving(args):
     # measured); at low load a batch is a single request either way
     srv = T.tang_server_create(0, n_streams=4, max_batch=262144, use_graphs=1)
     tags = [T.tang_server_add_ruleset(srv, rs) for _, rs, _ in sets]
+    for t in tags:   # every (ruleset, size class, slot) graph recorded before any request
+        T.tang_server_prepare(srv, t)
 
     def run(n_req, rate, seed):
         t_arr, sizes, tg = synth.make_requests(n_req, len(sets), seed=seed, rate_per_s=rate or 1.0)
@@ -1015,8 +1017,6 @@ def bench_serving(args):
                       "offered_req_per_s": rate, "submit_s": time.perf_counter() - t0}
 
     run(args.requests, 0, seed=1)  # warm-up
-    # idle time: the loop records the graphs of every (ruleset, size class, slot) then
-    time.sleep(2.0)
     reqs, sat = run(args.requests, 0, seed=2)
     mean_size = sat["packets"] / sat["requests"]
     sat_rate = sat["mpps"] * 1e6 / mean_size

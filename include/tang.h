@@ -341,6 +341,16 @@ int tang_server_create(int device, const tang_server_cfg_t* cfg, tang_server_t**
  */
 int tang_server_add_ruleset(tang_server_t* srv, tang_ruleset_t* rs, uint32_t* tag);
 /*
+ * Record the graphs of every batch size class on every stream slot for ruleset `tag`
+ * now, so that its requests do not pay for graph captures (otherwise each (size class,
+ * slot) pair is captured by its first batch). The loop does it while no request is
+ * pending and no batch is on the GPU; the call blocks until it is done. The same rule
+ * as for requests holds: no update or model load on the ruleset may overlap it. A later
+ * update or model load makes batches capture again. EINVAL on a bad tag, EBUSY if the
+ * server stops first.
+ */
+int tang_server_prepare(tang_server_t* srv, uint32_t tag);
+/*
  * Submit n host headers for ruleset `tag`; results go to host array out[n] when the
  * request completes. hdr and out must stay valid until then. EBUSY if the request can
  * never be admitted (larger than the limits), EINVAL on a bad tag.

@@ -10,10 +10,10 @@
 // A graph is recorded for the largest batch of its size class (a power of two); the
 // batch's real header count travels in the same host-to-device copy as its headers (the
 // first 16 bytes of the slot's staging) and the kernels read it from there, so a batch
-// costs the work of its own headers, not of its class. While no request is pending and
-// no batch is on the GPU, the loop records the graphs of every size class on every slot
-// for rulesets added since (one at a time, yielding as soon as a request arrives), so
-// that requests seldom pay for a graph capture.
+// costs the work of its own headers, not of its class. On request
+// (tang_server_prepare) the loop records the graphs of every size class on every slot
+// of a ruleset while no request is pending and no batch is on the GPU (yielding to
+// requests as they arrive), so that requests do not pay for graph captures.
 // Requests that arrive while others are on the GPU are admitted as slots and budget
 // free up, so batches of different requests and rulesets overlap on the device.
 #include <chrono>
@@ -86,7 +86,8 @@ struct tang_server_s {
     bool stop = false;
     std::thread th;
     std::vector<char> warmed;
-    std::vector<char> prepared;   // every (size class, slot) graph recorded once
+    std::vector<char> prepared;   // 0 not asked, 1 asked, 2 every (class, slot) graph recorded
+    std::condition_variable prepared_cv;
 
     void loop();
     void finish(StreamSlot& s, int status);
@@ -178,10 +179,11 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, tang_ruleset_t* rs, bool wa
     return TANG_OK;
 }
 
-// Idle-time preparation of ruleset `tag`: the eager first call (kernel attributes) if
-// needed, then the graph of every size class on every slot. Returns false if it stopped
-// early because a request arrived (it resumes at the next idle moment; recorded graphs
-// stay). Failures are left to the request path, which reports them.
+// Preparation of ruleset `tag` (asked for by tang_server_prepare, run by the loop while
+// idle): the eager first call (kernel attributes) if needed, then the graph of every
+// size class on every slot. Returns false if it stopped early because a request arrived
+// (it resumes at the next idle moment; recorded graphs stay). Failures are left to the
+// request path, which reports them.
 bool tang_server_s::prepare(uint32_t tag, tang_ruleset_t* rs, bool warm) {
     if (!cfg.use_graphs || rs->model.kind != 0) return true;
     StreamSlot& s0 = slots[0];
@@ -245,7 +247,10 @@ void tang_server_s::loop() {
         std::unique_lock<std::mutex> lk(mu);
         bool any_busy = false;
         for (auto& s : slots) any_busy |= s.busy;
-        if (stop && pending.empty() && !any_busy) break;
+        if (stop && pending.empty() && !any_busy) {
+            prepared_cv.notify_all();
+            break;
+        }
         for (uint32_t si = 0; si < slots.size() && !pending.empty(); ++si) {
             if (slots[si].busy) continue;
             // oldest request decides the ruleset; same-ruleset requests behind it join
@@ -289,14 +294,17 @@ void tang_server_s::loop() {
                 cv.wait_for(lk, std::chrono::microseconds(20));
             } else if (pending.empty() && !stop) {
                 uint32_t tag = 0;
-                while (tag < prepared.size() && prepared[tag]) ++tag;
+                while (tag < prepared.size() && prepared[tag] != 1) ++tag;
                 if (tag < prepared.size()) {
                     tang_ruleset_t* rs = rulesets[tag];
                     const bool warm = warmed[tag] != 0;
                     lk.unlock();
                     const bool done = prepare(tag, rs, warm);
                     lk.lock();
-                    if (done) prepared[tag] = 1;
+                    if (done) {
+                        prepared[tag] = 2;
+                        prepared_cv.notify_all();
+                    }
                 } else {
                     cv.wait_for(lk, std::chrono::milliseconds(50));
                 }
@@ -378,6 +386,18 @@ int tang_server_add_ruleset(tang_server_t* srv, tang_ruleset_t* rs, uint32_t* ta
     srv->rulesets.push_back(rs);
     srv->warmed.push_back(0);
     srv->prepared.push_back(0);
+    return TANG_OK;
+}
+
+int tang_server_prepare(tang_server_t* srv, uint32_t tag) {
+    if (!srv) return fail(TANG_EINVAL, "NULL server");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (tag >= srv->rulesets.size()) return fail(TANG_EINVAL, "unknown ruleset tag");
+    if (srv->stop) return fail(TANG_EBUSY, "server is stopping");
+    if (srv->prepared[tag] == 0) srv->prepared[tag] = 1;
+    srv->cv.notify_all();
+    srv->prepared_cv.wait(lk, [&] { return srv->prepared[tag] == 2 || srv->stop; });
+    if (srv->prepared[tag] != 2) return fail(TANG_EBUSY, "server stopped before the ruleset was prepared");
     return TANG_OK;
 }
 

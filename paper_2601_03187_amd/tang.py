@@ -109,6 +109,7 @@ _sigs = {
     "tang_last_error": (ctypes.c_char_p, []),
     "tang_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(tang_server_cfg_t), ctypes.POINTER(_P)]),
     "tang_server_add_ruleset": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_uint32)]),
+    "tang_server_prepare": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "tang_server_submit": (ctypes.c_int, [_P, ctypes.c_uint32, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
     "tang_server_wait": (ctypes.c_int, [_P, ctypes.c_int64]),
     "tang_server_poll": (ctypes.c_int, [_P]),
@@ -418,6 +419,11 @@ def tang_server_add_ruleset(srv: int, rs: int) -> int:
     t = ctypes.c_uint32()
     _check(_lib.tang_server_add_ruleset(srv, rs, ctypes.byref(t)))
     return int(t.value)
+
+
+def tang_server_prepare(srv: int, tag: int) -> None:
+    """Record every (size class, slot) graph of ruleset `tag` now (blocks until done)."""
+    _check(_lib.tang_server_prepare(srv, tag))
 
 
 def tang_server_submit(srv: int, tag: int, hdr: np.ndarray, out: np.ndarray) -> int:

@@ -155,3 +155,40 @@ def test_alone_equals_mix_at_serving_sizes():
         T.tang_server_destroy(srv)
         for _, rs in sets:
             T.tang_ruleset_destroy(rs)
+
+
+def test_prepared_graphs_serve_every_size_class():
+    """tang_server_prepare records the graph of every size class on every slot; requests
+    of every class afterwards (one header below, at and above each power of two, so the
+    live count differs from the class), and again after a new model bumps the ruleset's
+    version, all equal the oracle's answers. A bad tag is refused."""
+    torch_cuda()
+    rules = synth.make_rules(3000, seed=810)
+    rs = T.tang_ruleset_create(0, rules)
+    C = T.tang_ruleset_num_tuples(rs)
+    Ws, bs = train.random_weights(C, 256, seed=11)
+    T.tang_model_load(rs, Ws, bs, "bf16")
+    srv = T.tang_server_create(0, n_streams=2, max_batch=8192, use_graphs=1)
+    try:
+        tag = T.tang_server_add_ruleset(srv, rs)
+        T.tang_server_prepare(srv, tag)
+        T.tang_server_prepare(srv, tag)   # already prepared: returns at once
+        with pytest.raises(T.TangError) as e:
+            T.tang_server_prepare(srv, tag + 1)
+        assert e.value.name == "EINVAL"
+        sizes = sorted({max(1, min(8192, (1 << p) + d)) for p in range(5, 14) for d in (-1, 0, 1)})
+        for round_ in range(2):
+            reqs = []
+            for q, n in enumerate(sizes):
+                hdr = synth.make_packets(rules, n, seed=4000 + 100 * round_ + q, frac_in=0.8)
+                out = np.full(n, 0xDEADBEEF, dtype=np.uint32)
+                reqs.append((hdr, out, T.tang_server_submit(srv, tag, hdr, out)))
+            for hdr, out, r in reqs:
+                T.tang_server_wait(r, 60_000_000)
+                assert np.array_equal(out, orc.classify(rules, hdr)), (round_, len(hdr))
+                T.tang_server_req_free(r)
+            Wf, bf = train.random_weights(C, 256, seed=12)
+            T.tang_model_load(rs, Wf, bf, "bf16", topk=2)
+    finally:
+        T.tang_server_destroy(srv)
+        T.tang_ruleset_destroy(rs)
