@@ -397,7 +397,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                 for (int nt = 0; nt < NT; ++nt) z[mt][nt] = mma(A, a1[kb][nt], z[mt][nt]);
             }
         };
-        auto issue_group = [&](int mt0, f4 (&acc)[TG][NT]) {
+#pragma unroll
+        for (int mt0 = 0; mt0 < MTH; mt0 += TG) {
+            f4 acc[TG][NT];
 #pragma unroll
             for (int u = 0; u < TG; ++u) {
                 const f4 b0 = acc_init<PREC>(sbv + H, mt0 + u, g);
@@ -413,8 +415,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                     for (int nt = 0; nt < NT; ++nt) acc[u][nt] = mma(A, a0[kb][nt], acc[u][nt]);
                 }
             }
-        };
-        auto finish_group = [&](int mt0, f4 (&acc)[TG][NT]) {
 #pragma unroll
             for (int u = 0; u < TG; ++u)
                 epi_hidden<PREC, NT, KBNH>(acc[u], mt0 + u, sbv + H, a.hs[1], g, a1);
@@ -432,59 +432,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                     }
                 }
             }
-        };
-        // SWP: the next group's MFMAs are issued before this group's epilogue, in one
-        // scheduling region, so that its conversions fill the matrix pipe's shadow
-        constexpr bool SWP = false;
-        if constexpr (SWP) {
-            f4 accp[2][TG][NT];
-            issue_group(0, accp[0]);
-#pragma unroll
-            for (int gi = 0; gi < MTH / TG; ++gi) {
-                if (gi + 1 < MTH / TG) issue_group((gi + 1) * TG, accp[(gi + 1) & 1]);
-                finish_group(gi * TG, accp[gi & 1]);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        } else {
-#pragma unroll
-            for (int mt0 = 0; mt0 < MTH; mt0 += TG) {
-                f4 acc[TG][NT];
-#pragma unroll
-                for (int u = 0; u < TG; ++u) {
-                    const f4 b0 = acc_init<PREC>(sbv + H, mt0 + u, g);
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) acc[u][nt] = b0;
-                }
-#pragma unroll
-                for (int kb = 0; kb < KBNH; ++kb) {
-#pragma unroll
-                    for (int u = 0; u < TG; ++u) {
-                        const F A = ldf<(LDSM & 2) != 0>(s2, r2, (mt0 + u) * KBNH + kb, lane, sbase, win);
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt) acc[u][nt] = mma(A, a0[kb][nt], acc[u][nt]);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < TG; ++u)
-                    epi_hidden<PREC, NT, KBNH>(acc[u], mt0 + u, sbv + H, a.hs[1], g, a1);
-                if constexpr (OUTB == 1) {
-#pragma unroll
-                    for (int u = 0; u < TG; ++u) {
-                        const int mt = mt0 + u;
-                        if constexpr (KB >= 16) {
-                            if ((mt + 1) % (KB / 16) == 0) layer3_block(mt / (KB / 16));
-                        } else {
-#pragma unroll
-                            for (int q = 0; q < 16 / KB; ++q) layer3_block((16 / KB) * mt + q);
-                        }
-                    }
-                }
-                // FP8 groups are left to the scheduler, which then overlaps one group's
-                // scale / clamp / conversion epilogue with the next group's MFMAs (chunked
-                // classify 3.17 -> 3.07 ms per 16M headers); for BF16 the same freedom was
-                // slower (predictor 2.48 -> 2.60 ms)
-                if constexpr (PREC != TANG_FP8) __builtin_amdgcn_sched_barrier(0);
-            }
+            // FP8 groups are left to the scheduler, which then overlaps one group's scale /
+            // clamp / conversion epilogue with the next group's MFMAs (chunked classify
+            // 3.17 -> 3.07 ms per 16M headers); for BF16 the same freedom was slower
+            // (predictor 2.48 -> 2.60 ms)
+            if constexpr (PREC != TANG_FP8) __builtin_amdgcn_sched_barrier(0);
         }
         // layer 3: H -> C in blocks of 32 classes (two 16-row tiles). With one block each
         // lane's 8 scores go straight to the top-k; with more, each lane keeps a running
