@@ -366,7 +366,11 @@ int tang_server_req_times(const tang_req_t* req, uint64_t* submit_ns, uint64_t* 
                           uint64_t* done_ns);
 /* Frees the handle; a request still running completes (hdr and out must stay valid). */
 void tang_server_req_free(tang_req_t* req);
-/* Drains pending work, stops the loop, frees the server (not the rulesets). */
+/*
+ * Drains pending work, stops the loop, frees the server (not the rulesets). No other
+ * call on the same server may be in progress or follow (request handles stay valid:
+ * wait, poll, times and free work on them after the server is gone).
+ */
 int tang_server_destroy(tang_server_t* srv);
 
 #ifdef __cplusplus
