@@ -342,8 +342,9 @@ int tang_server_create(int device, const tang_server_cfg_t* cfg, tang_server_t**
 int tang_server_add_ruleset(tang_server_t* srv, tang_ruleset_t* rs, uint32_t* tag);
 /*
  * Record the graphs of every batch size class on every stream slot for ruleset `tag`
- * now, so that its requests do not pay for graph captures (otherwise each (size class,
- * slot) pair is captured by its first batch). The loop does it while no request is
+ * now, and launch each once on an empty batch, so that its requests do not pay for graph
+ * captures or first launches (otherwise each (size class, slot) pair is captured by its
+ * first batch). The loop does it while no request is
  * pending and no batch is on the GPU; the call blocks until it is done. The same rule
  * as for requests holds: no update or model load on the ruleset may overlap it. A later
  * update or model load makes batches capture again. EINVAL on a bad tag, EBUSY if the

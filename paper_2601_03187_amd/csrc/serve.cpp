@@ -4,16 +4,22 @@
 // and device buffers for one batch. While a slot is free and requests are pending, the
 // loop takes the oldest pending request, packs further pending requests of the same
 // ruleset behind it (arrival order, up to the batch limit), admits them if the packets
-// and staging bytes in flight stay within the configured limits, copies their headers
-// in, replays the HIP graph captured for (ruleset, batch size class, slot), copies the
-// results out and records an event. Completed slots hand results to their requests.
+// and staging bytes in flight stay within the configured limits, writes their headers
+// into the slot's pinned staging, replays the HIP graph captured for (ruleset, batch size
+// class, slot) and records an event. Completed slots hand results to their requests.
+// The graph moves the batch itself: a first kernel pulls the headers from the pinned
+// staging into device memory, a last one pushes the rule ids back, so that a batch costs
+// one graph launch and no runtime copy (asynchronous runtime copies have been seen to
+// hold the calling thread for 6-11 ms now and then, which stalled admission for every
+// slot).
 // A graph is recorded for the largest batch of its size class (a power of two); the
-// batch's real header count travels in the same host-to-device copy as its headers (the
-// first 16 bytes of the slot's staging) and the kernels read it from there, so a batch
+// batch's real header count travels with its headers (the first 16 bytes of the slot's
+// staging) and the kernels read it from there, so a batch
 // costs the work of its own headers, not of its class. On request
 // (tang_server_prepare) the loop records the graphs of every size class on every slot
 // of a ruleset while no request is pending and no batch is on the GPU (yielding to
-// requests as they arrive), so that requests do not pay for graph captures.
+// requests as they arrive) and launches each once on an empty batch, so that requests
+// pay neither for graph captures nor for first launches.
 // Requests that arrive while others are on the GPU are admitted as slots and budget
 // free up, so batches of different requests and rulesets overlap on the device.
 #include <chrono>
@@ -48,9 +54,12 @@ struct StreamSlot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     // staging of max_batch + 1 headers: element 0 carries the live count in its first
-    // word, the batch's headers follow
+    // word, the batch's headers follow; the pinned host halves are coherent host memory
+    // that the staging kernels read and write through their device addresses (dh_*)
     tang_header_t* h_buf = nullptr;  // pinned
     uint32_t* h_out = nullptr;       // pinned
+    const tang_header_t* dh_buf = nullptr;
+    uint32_t* dh_out = nullptr;
     tang_header_t* d_buf = nullptr;
     uint32_t* d_out = nullptr;
     tang_header_t* h_hdr() const { return h_buf + 1; }
@@ -66,6 +75,48 @@ struct GraphEntry {
     uint64_t version = ~0ull;
     hipGraphExec_t exec = nullptr;
 };
+
+constexpr uint32_t kStageThreads = 256;
+constexpr uint32_t kInPerThread = 4;    // headers per thread of k_stage_in
+constexpr uint32_t kOutPerThread = 4;   // rule ids per thread of k_stage_out
+
+// Pulls a batch from pinned host staging into device memory: element 0 (the live count
+// in its first word) and then the live headers, kInPerThread 16-byte headers per thread
+// (all loads issued before the stores: reads of host memory are long round trips);
+// threads past the live count (or the launch's capacity) do nothing.
+__global__ void __launch_bounds__(kStageThreads)
+k_stage_in(const uint4* __restrict__ h_buf, uint4* __restrict__ d_buf, uint32_t cap) {
+    const uint4 head = h_buf[0];
+    const uint32_t live = min(head.x, cap);
+    const uint32_t i0 = blockIdx.x * kStageThreads * kInPerThread + threadIdx.x;
+    if (i0 == 0) d_buf[0] = head;
+    uint4 v[kInPerThread];
+#pragma unroll
+    for (uint32_t k = 0; k < kInPerThread; ++k) {
+        const uint32_t i = i0 + k * kStageThreads;
+        if (i < live) v[k] = h_buf[1 + i];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kInPerThread; ++k) {
+        const uint32_t i = i0 + k * kStageThreads;
+        if (i < live) d_buf[1 + i] = v[k];
+    }
+}
+
+// Pushes the batch's rule ids to pinned host memory, kOutPerThread (4) per thread (one
+// 16-byte store where all four are live); the live count is the one k_stage_in wrote.
+__global__ void __launch_bounds__(kStageThreads)
+k_stage_out(const uint32_t* __restrict__ d_live, const uint32_t* __restrict__ d_out,
+            uint32_t* __restrict__ h_out, uint32_t cap) {
+    const uint32_t live = min(d_live[0], cap);
+    static_assert(kOutPerThread == 4, "one 16-byte store per thread");
+    const uint32_t j = kOutPerThread * (blockIdx.x * kStageThreads + threadIdx.x);
+    if (j + kOutPerThread <= live) {
+        *reinterpret_cast<uint4*>(h_out + j) = *reinterpret_cast<const uint4*>(d_out + j);
+    } else {
+        for (uint32_t k = j; k < live; ++k) h_out[k] = d_out[k];
+    }
+}
 
 }  // namespace
 
@@ -96,6 +147,7 @@ struct tang_server_s {
     int graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uint32_t slot_idx,
                   hipGraphExec_t* out);
     bool prepare(uint32_t tag, tang_ruleset_t* rs, bool warm);
+    int run_batch(tang_ruleset_t* rs, StreamSlot& s, size_t cap, bool live_count);
 };
 
 using namespace tang;
@@ -118,7 +170,7 @@ int tang_server_s::graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uin
     }
     StreamSlot& s = slots[si];
     TANG_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeRelaxed));
-    int rc = classify_async(rs, s.d_hdr(), s.d_out, cls, s.stream, nullptr, false, s.d_live());
+    int rc = run_batch(rs, s, cls, true);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s.stream, &graph);
     if (rc) {
@@ -134,6 +186,26 @@ int tang_server_s::graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uin
     }
     g.version = rs->version;
     *out = g.exec;
+    return TANG_OK;
+}
+
+// One batch of up to `cap` headers on the slot's stream: the headers in, the
+// classification, the rule ids out. With `live_count` the kernels take the batch's size
+// from the staging (launches sized for `cap`, as a graph records them); without it `cap`
+// is the batch's size.
+int tang_server_s::run_batch(tang_ruleset_t* rs, StreamSlot& s, size_t cap, bool live_count) {
+    const uint32_t c = (uint32_t)cap;   // cap <= max_batch, a 32-bit value
+    constexpr uint32_t in_blk = kInPerThread * kStageThreads, out_blk = kOutPerThread * kStageThreads;
+    hipLaunchKernelGGL(k_stage_in, dim3((c + in_blk - 1) / in_blk), dim3(kStageThreads),
+                       0, s.stream, reinterpret_cast<const uint4*>(s.dh_buf),
+                       reinterpret_cast<uint4*>(s.d_buf), c);
+    TANG_HIP(hipGetLastError());
+    int rc = classify_async(rs, s.d_hdr(), s.d_out, cap, s.stream, nullptr, false,
+                            live_count ? s.d_live() : nullptr);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_stage_out, dim3((c + out_blk - 1) / out_blk),
+                       dim3(kStageThreads), 0, s.stream, s.d_live(), s.d_out, s.dh_out, c);
+    TANG_HIP(hipGetLastError());
     return TANG_OK;
 }
 
@@ -154,10 +226,8 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, tang_ruleset_t* rs, bool wa
     const uint32_t live = (uint32_t)total;   // total <= max_batch, a 32-bit value
     s.h_buf[0] = tang_header_t{};
     std::memcpy(&s.h_buf[0], &live, sizeof live);
-    TANG_HIP(hipMemcpyAsync(s.d_buf, s.h_buf, (total + 1) * sizeof(tang_header_t),
-                            hipMemcpyHostToDevice, s.stream));
-    if (!warm) {  // first use: eager call sets up kernel attributes before any capture
-        int rc = classify_async(rs, s.d_hdr(), s.d_out, total, s.stream, nullptr, false);
+    if (!warm) {  // first use: an eager batch sets up kernel attributes before any capture
+        int rc = run_batch(rs, s, total, false);
         if (rc) return rc;
         TANG_HIP(hipStreamSynchronize(s.stream));
     }
@@ -169,11 +239,9 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, tang_ruleset_t* rs, bool wa
         if (rc) return rc;
         TANG_HIP(hipGraphLaunch(exec, s.stream));
     } else {
-        int rc = classify_async(rs, s.d_hdr(), s.d_out, total, s.stream, nullptr, false);
+        int rc = run_batch(rs, s, total, false);
         if (rc) return rc;
     }
-    TANG_HIP(hipMemcpyAsync(s.h_out, s.d_out, total * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                            s.stream));
     TANG_HIP(hipEventRecord(s.ev, s.stream));
     s.busy = true;
     return TANG_OK;
@@ -193,7 +261,11 @@ bool tang_server_s::prepare(uint32_t tag, tang_ruleset_t* rs, bool warm) {
         std::lock_guard<std::mutex> g(mu);
         warmed[tag] = 1;
     }
+    // the graphs of a slot, once recorded, are each launched once (a graph's first launch
+    // costs more than a replay) with a live count of 0 in the slot's staging, so their
+    // kernels return at once; the stream is drained before the loop uses the slot again
     for (uint32_t si = 0; si < slots.size(); ++si) {
+        std::vector<hipGraphExec_t> execs;
         for (uint64_t cls = 32; cls <= cfg.max_batch; cls <<= 1) {
             {
                 std::lock_guard<std::mutex> g(mu);
@@ -201,7 +273,15 @@ bool tang_server_s::prepare(uint32_t tag, tang_ruleset_t* rs, bool warm) {
             }
             hipGraphExec_t exec = nullptr;
             if (graph_for(tag, rs, (uint32_t)cls, si, &exec) != TANG_OK) return true;
+            execs.push_back(exec);
         }
+        StreamSlot& s = slots[si];
+        s.h_buf[0] = tang_header_t{};
+        hipError_t e = hipSuccess;
+        for (size_t k = 0; k < execs.size() && e == hipSuccess; ++k)
+            e = hipGraphLaunch(execs[k], s.stream);
+        (void)hipStreamSynchronize(s.stream);
+        if (e != hipSuccess) return true;
     }
     return true;
 }
@@ -358,8 +438,11 @@ int tang_server_create(int device, const tang_server_cfg_t* cfg, tang_server_t**
             if (e == hipSuccess) e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
             const size_t stage = ((size_t)c.max_batch + 1) * sizeof(tang_header_t);
-            if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_buf, stage, 0);
-            if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_out, c.max_batch * sizeof(uint32_t), 0);
+            if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_buf, stage, hipHostMallocCoherent);
+            if (e == hipSuccess)
+                e = hipHostMalloc((void**)&s.h_out, c.max_batch * sizeof(uint32_t), hipHostMallocCoherent);
+            if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&s.dh_buf, s.h_buf, 0);
+            if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&s.dh_out, s.h_out, 0);
             if (e == hipSuccess) e = dev_alloc(&s.d_buf, stage);
             if (e == hipSuccess) e = dev_alloc(&s.d_out, c.max_batch * sizeof(uint32_t));
             if (e == hipSuccess) e = hipMemset(s.d_buf, 0, stage);
