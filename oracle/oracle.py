@@ -37,6 +37,7 @@ Contents, each written from the passage it cites:
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -221,16 +222,31 @@ E4M3_MAX = 448.0
 # h_l = ReLU(z_l) for hidden layers, logits = z_L. W_l is [out][in] (PyTorch Linear).
 
 def fp8_weight_scale(W: np.ndarray) -> float:
-    """Per-layer weight scale: amax(|W|) / 448 (1 for an all-zero layer), as fp32."""
+    """Per-layer weight scale: amax(|W|) / 448 (1 for an all-zero layer), as fp32. The
+    output layer uses it as is."""
     amax = float(np.max(np.abs(W))) if W.size else 0.0
     return float(np.float32(amax / E4M3_MAX)) if amax > 0 else 1.0
 
 
+def fp8_hidden_weight_scale(W: np.ndarray, s_a: float, s_next: float) -> float:
+    """Weight scale of a hidden layer whose input scale is s_a and whose output feeds a
+    layer of input scale s_next: the amax scale s raised by a factor in [1, 2) so that the
+    requantisation factor s_w s_a / s_next is a power of two 2^e, the least one not below
+    s s_a / s_next; s_w = 2^e s_next / s_a, as fp32. (The layer's output then enters the
+    next layer as E4M3(2^e (product sum + b / (s_a s_w))), a scaling without rounding.)"""
+    s = fp8_weight_scale(W)
+    k = float(s) * float(s_a) / float(s_next)
+    mant, ex = math.frexp(k)          # k = mant 2^ex, mant in [0.5, 1)
+    e = ex - 1 if mant == 0.5 else ex
+    return float(np.float32(math.ldexp(float(s_next) / float(s_a), e)))
+
+
 def mlp_forward(x: np.ndarray, Ws, bs, precision: str = "fp32", act_scales=None) -> np.ndarray:
     """Logits in float64. precision: fp32 (no rounding), bf16 (weights and layer inputs
-    rounded to bfloat16), fp8 (weights scaled by amax/448 and layer inputs scaled by the
-    given per-layer activation scale, both rounded to E4M3 with saturation; the product
-    sum is multiplied back by s_a * s_w). Biases stay unrounded."""
+    rounded to bfloat16), fp8 (layer inputs scaled by the given per-layer activation scale
+    and weights by their layer's weight scale -- ``fp8_hidden_weight_scale`` for the
+    hidden layers, amax/448 for the output layer -- both rounded to E4M3 with saturation;
+    the product sum is multiplied back by s_a * s_w). Biases stay unrounded."""
     a = np.asarray(x, dtype=np.float64)
     L = len(Ws)
     for l in range(L):
@@ -241,8 +257,10 @@ def mlp_forward(x: np.ndarray, Ws, bs, precision: str = "fp32", act_scales=None)
         elif precision == "bf16":
             z = bf16_round(a) @ bf16_round(W).T + b
         elif precision == "fp8":
-            s_w = fp8_weight_scale(W)
-            s_a = 1.0 if l == 0 else float(act_scales[l])
+            # activation scales are fp32 values (the library's interface type)
+            s_a = 1.0 if l == 0 else float(np.float32(act_scales[l]))
+            s_w = (fp8_hidden_weight_scale(W, s_a, float(np.float32(act_scales[l + 1])))
+                   if l < L - 1 else fp8_weight_scale(W))
             inv_a = float(np.float32(1.0 / s_a))
             inv_w = float(np.float32(1.0 / s_w))
             qa = e4m3_round(a * inv_a)

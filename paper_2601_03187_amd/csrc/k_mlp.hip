@@ -47,7 +47,11 @@ struct MlpArgs {
     uint32_t nbias;   // biases stored: 2 H + 32 x class blocks
     float deq[3];
     float inv_a[3];
-    float hs[2];  // FP8 hidden layers: deq[l] * inv_a[l + 1] (product scale into next input)
+    // FP8 hidden layers: the requantisation factor into the next layer's input is 2^e;
+    // rq = 2^-e is the scaled conversion's operand, rb = 448 * 2^-e the clamp bound in
+    // accumulator units
+    float rq[2];
+    float rb[2];
 };
 
 namespace {
@@ -79,10 +83,14 @@ __device__ __forceinline__ uint32_t relu_bf16x2(uint32_t p) {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p),
                                                                   (s16x2){0, 0}));
 }
-// Four non-negative floats (already clamped to <= 448) -> four E4M3 bytes, RNE.
-__device__ __forceinline__ uint32_t pack_fp8(float a, float b, float c, float d) {
-    uint32_t v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);
+// Four non-negative floats x (already clamped to x 2^e <= 448) -> the four E4M3 bytes of
+// x 2^e, RNE, for rq = 2^-e: the scaled conversion divides by the power of two of its
+// scale operand, which is exact, so the only rounding is the one onto E4M3.
+__device__ __forceinline__ uint32_t pack_fp8(float a, float b, float c, float d, float rq) {
+    s16x2 v = {0, 0};
+    v = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(v, a, b, rq, false);
+    v = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(v, c, d, rq, true);
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 // Header words in MSB-first byte order: SIP, DIP, SP:DP, PROTO:0:0:0.
@@ -195,21 +203,20 @@ __device__ __forceinline__ F ldf(const F* lds, __amdgpu_buffer_rsrc_t r, uint32_
     }
 }
 
-// Accumulator start of one 16-row output tile: FP32 and BF16 layers fold the bias in as
-// the MFMA's C operand (the four rows this lane holds); FP8 products are scaled first, so
-// their bias is added in the epilogue.
+// Accumulator start of one 16-row output tile: hidden layers fold the bias in as the
+// MFMA's C operand (the four rows this lane holds; FP8 biases are stored in accumulator
+// units, b / (s_a s_w)).
 template <int PREC>
 __device__ __forceinline__ f4 acc_init(const float* sbias, int mt, int g) {
-    if constexpr (PREC == TANG_FP8) return (f4){0, 0, 0, 0};
-    else return *reinterpret_cast<const f4*>(sbias + 16 * mt + 4 * g);
+    return *reinterpret_cast<const f4*>(sbias + 16 * mt + 4 * g);
 }
 
 // ReLU of one 16-row output tile and conversion into the next layer's B operand. FP8:
-// relu(acc * deq + b) * inv_next, clamped to 448, as one FMA with the folded scale
-// hs = deq * inv_next and the prescaled bias b * inv_next, and one median-of-three.
+// the next input is E4M3(2^e relu(acc)) clamped to 448: one median-of-three against
+// [0, rb = 448 2^-e] and the scaled conversion by rq = 2^-e (two values per instruction).
 template <int PREC, int NT, int KBN>
-__device__ __forceinline__ void epi_hidden(const f4 (&acc)[NT], int mt, const float* sbias, float hs,
-                                           int g, typename FragT<PREC>::T (&dst)[KBN][NT]) {
+__device__ __forceinline__ void epi_hidden(const f4 (&acc)[NT], int mt, float rq, float rb,
+                                           typename FragT<PREC>::T (&dst)[KBN][NT]) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         if constexpr (PREC == TANG_FP32) {
@@ -219,13 +226,11 @@ __device__ __forceinline__ void epi_hidden(const f4 (&acc)[NT], int mt, const fl
             dst[mt >> 1][nt][2 * (mt & 1)] = relu_bf16x2(pack_bf16(acc[nt][0], acc[nt][1]));
             dst[mt >> 1][nt][2 * (mt & 1) + 1] = relu_bf16x2(pack_bf16(acc[nt][2], acc[nt][3]));
         } else {
-            const f4 bv = *reinterpret_cast<const f4*>(sbias + 16 * mt + 4 * g);
             float v[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                v[r] = __builtin_amdgcn_fmed3f(__builtin_fmaf(acc[nt][r], hs, bv[r]), 0.0f, 448.0f);
+            for (int r = 0; r < 4; ++r) v[r] = __builtin_amdgcn_fmed3f(acc[nt][r], 0.0f, rb);
             // a 128-wide K block holds the rows of 8 consecutive output tiles
-            dst[mt >> 3][nt][mt & 7] = pack_fp8(v[0], v[1], v[2], v[3]);
+            dst[mt >> 3][nt][mt & 7] = pack_fp8(v[0], v[1], v[2], v[3], rq);
         }
     }
 }
@@ -331,7 +336,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
                 for (int f = 0; f < 12; ++f)
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) acc[nt] = mma(wf[f], xb[f / 3][nt], acc[nt]);
-                epi_hidden<PREC, NT, KBNH>(acc, mt, sbv, a.hs[0], g, a0);
+                epi_hidden<PREC, NT, KBNH>(acc, mt, a.rq[0], a.rb[0], a0);
                 __builtin_amdgcn_sched_barrier(0);
             }
         } else {
@@ -372,7 +377,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[nt] = mma(cur[kb], bits[kb][nt], acc[nt]);
             }
-            epi_hidden<PREC, NT, KBNH>(acc, mt, sbv, a.hs[0], g, a0);
+            epi_hidden<PREC, NT, KBNH>(acc, mt, a.rq[0], a.rb[0], a0);
             // keep the scheduler from hoisting every tile's fragment loads (register blow-up)
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -417,7 +422,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp(
             }
 #pragma unroll
             for (int u = 0; u < TG; ++u)
-                epi_hidden<PREC, NT, KBNH>(acc[u], mt0 + u, sbv + H, a.hs[1], g, a1);
+                epi_hidden<PREC, NT, KBNH>(acc[u], mt0 + u, a.rq[1], a.rb[1], a1);
             if constexpr (OUTB == 1) {
                 // output tile mt feeds K block mt / (KB / 16) (KB >= 16), or the four
                 // blocks 4 mt .. 4 mt + 3 (FP32, KB = 4)
@@ -650,8 +655,19 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
             float amax = 0.0f;
             for (size_t k = 0; k < (size_t)outs[l] * ins[l]; ++k) amax = std::max(amax, std::fabs(W[l][k]));
             s_w = amax > 0.0f ? amax / 448.0f : 1.0f;
-            inv_w = 1.0f / s_w;
             s_a = l == 0 ? 1.0f : act_scales[l];
+            if (l < 2) {
+                // hidden layer: the weight scale is raised by a factor in [1, 2) until the
+                // requantisation factor s_w s_a / s_next is a power of two, 2^e
+                const double s_n = act_scales[l + 1];
+                int ex = 0;
+                const double mant = std::frexp((double)s_w * (double)s_a / s_n, &ex);
+                const int e = mant == 0.5 ? ex - 1 : ex;
+                if (e < -100 || e > 100) return fail(TANG_EINVAL, "FP8 scales too far apart (|e| > 100)");
+                s_w = (float)std::ldexp(s_n / (double)s_a, e);
+                m.rq[l] = std::ldexp(1.0f, -e);
+            }
+            inv_w = 1.0f / s_w;
             m.deq[l] = s_a * s_w;
             m.inv_a[l] = 1.0f / s_a;
         }
@@ -715,11 +731,11 @@ int model_prepare(tang_ruleset_t* rs, const tang_mlp_desc_t* d, const float* con
         if (e != hipSuccess) { model_free(m); return hip_fail(e, "model upload"); }
         m.bytes += x3.size() * 2;
     }
-    // FP8 hidden biases are stored prescaled by the next layer's inverse activation scale
+    // FP8 hidden biases are stored in accumulator units, b / (s_a s_w)
     std::vector<float> bias(2 * H + CP, 0.0f);
     for (int k = 0; k < H; ++k) {
-        bias[k] = p == TANG_FP8 ? b[0][k] * m.inv_a[1] : b[0][k];
-        bias[H + k] = p == TANG_FP8 ? b[1][k] * m.inv_a[2] : b[1][k];
+        bias[k] = p == TANG_FP8 ? (float)((double)b[0][k] / (double)m.deq[0]) : b[0][k];
+        bias[H + k] = p == TANG_FP8 ? (float)((double)b[1][k] / (double)m.deq[1]) : b[1][k];
     }
     for (int k = 0; k < C; ++k) bias[2 * H + k] = b[2][k];
     hipError_t e = dev_alloc(&m.bias, bias.size() * 4);
@@ -769,7 +785,7 @@ hipError_t launch_t(const ModelDev& m, const tang_header_t* d_hdr, uint32_t n, u
     a.n3 = m.w3frags;
     a.nbias = 2 * H + kOutPad * ((m.n_out + kOutPad - 1) / kOutPad);
     for (int l = 0; l < 3; ++l) { a.deq[l] = m.deq[l]; a.inv_a[l] = m.inv_a[l]; }
-    for (int l = 0; l < 2; ++l) a.hs[l] = m.deq[l] * m.inv_a[l + 1];
+    for (int l = 0; l < 2; ++l) { a.rq[l] = m.rq[l]; a.rb[l] = 448.0f * m.rq[l]; }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WAVES), lds, s,
                        reinterpret_cast<const uint4*>(d_hdr), n, (const F*)m.w[0], (const F*)m.w[1],
                        (const F*)m.w[2], (const u32x4*)m.w1x3, m.bias, a, cand, logits, cand16, live);

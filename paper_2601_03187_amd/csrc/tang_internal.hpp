@@ -210,6 +210,7 @@ struct ModelDev {
     float* bias = nullptr;   // [hidden | hidden | 32] floats
     float deq[3] = {1, 1, 1};     // FP8: s_a * s_w per layer
     float inv_a[3] = {1, 1, 1};   // FP8: 1 / s_a per layer (layer 0 unused)
+    float rq[2] = {1, 1};         // FP8 hidden layers: 2^-e, e the requantisation exponent
     // Residual network: input layer FP32 [512][8], BF16 layer weights, BF16 activation
     // workspace (three chunk buffers) and the event that orders calls sharing it.
     int n_blocks = 0;

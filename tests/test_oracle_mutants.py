@@ -16,7 +16,8 @@ from tests.test_oracle_resnet_pins import WIDTH_TWO_MAGS, width_two_network
 
 MLP_MISTAKES = ["bf16_no_weight_round", "bf16_no_input_round", "bf16_round_bias",
                 "bf16_round_logits", "fp8_no_weight_round", "fp8_no_act_round",
-                "fp8_no_saturate", "fp8_scales_layer0", "fp8_deq_weight_only",
+                "fp8_no_saturate", "fp8_scales_layer0", "fp8_amax_scale_hidden",
+                "fp8_deq_weight_only",
                 "fp8_deq_act_only", "relu_on_logits", "no_bias", "no_relu"]
 
 
@@ -43,8 +44,12 @@ def _mlp_copy(x, Ws, bs, precision="fp32", act_scales=None, mistake=None):
             z = qa @ qw.T + qb
         elif precision == "fp8":
             rnd = _e4m3_unsaturated if mistake == "fp8_no_saturate" else orc.e4m3_round
-            s_w = orc.fp8_weight_scale(W)
-            s_a = float(act_scales[l]) if (l > 0 or mistake == "fp8_scales_layer0") else 1.0
+            s_a = (float(np.float32(act_scales[l])) if (l > 0 or mistake == "fp8_scales_layer0")
+                   else 1.0)
+            if l < L - 1 and mistake != "fp8_amax_scale_hidden":
+                s_w = orc.fp8_hidden_weight_scale(W, s_a, float(np.float32(act_scales[l + 1])))
+            else:
+                s_w = orc.fp8_weight_scale(W)
             inv_a = float(np.float32(1.0 / s_a))
             inv_w = float(np.float32(1.0 / s_w))
             qa = a * inv_a if mistake == "fp8_no_act_round" else rnd(a * inv_a)

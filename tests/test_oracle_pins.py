@@ -292,9 +292,11 @@ def test_mlp_one_hot_selects_weight_column_and_relu_clips():
 
 
 # --- Quantisation steps of the predictor (reading R19: BF16 round-to-nearest-even of the
-# weights and of every layer's input; FP8 E4M3 with a per-layer weight scale amax/448 and
-# static activation scales, FP32 accumulate and bias). Each case is worked out by hand
-# and isolates one step, so dropping or misplacing that step changes the pinned value.
+# weights and of every layer's input; FP8 E4M3 with static activation scales, a weight
+# scale amax/448 for the output layer and, for a hidden layer, that scale raised by a
+# factor in [1, 2) until s_w s_a / s_next is a power of two; FP32 accumulate and bias).
+# Each case is worked out by hand and isolates one step, so dropping or misplacing that
+# step changes the pinned value.
 # The cases are shared with tests/test_oracle_mutants.py, which checks that a copy of the
 # oracle with each step broken fails at least one of them.
 
@@ -321,30 +323,45 @@ def mlp_quant_cases():
     cases.append(("bf16_input", "bf16", [W1, np.ones((1, 1)), np.ones((1, 1))],
                   [np.array([2.0 ** -9]), np.zeros(1), np.array([0.5 + 2.0 ** -10])],
                   None, [1.5 + 2.0 ** -10]))
-    # FP8 weight rounding, in the output layer: W1 column = [1, 1] and W2 = I scale to
-    # 448 (s_w = 1/448) and give hidden values [1, 1], which s_a = 1/448 maps to 448 (on
-    # the grid). W3 = diag(3, 1) has s_w = 3/448, so its scaled entries are 448 and
-    # 149.33; E4M3 has 144 and 160 in [128, 256) (step 16), so 149.33 -> 144 and the
-    # logits are 448 * 448 * (1/448) * (3/448) = 3 and 448 * 144 * ... = 27/28.
+    # FP8 weight rounding, in the output layer: W1 column = [1, 1] scales to 448 (s_w =
+    # 1/448: with s_a = 1 and s_next = 1/448 the factor is already 2^0) and W2 = I to 256
+    # (amax scale 1/448, factor (1/448)(1/448)/(1/448) = 1/448, raised to 2^-8: s_w =
+    # 2^-8); the hidden values [1, 1] enter each next layer as 448 (s_a = 1/448, on the
+    # grid). W3 = diag(3, 1) has s_w = 3/448, so its scaled entries are 448 and 149.33;
+    # E4M3 has 144 and 160 in [128, 256) (step 16), so 149.33 -> 144 and the logits are
+    # 448 * 448 * (1/448) * (3/448) = 3 and 448 * 144 * ... = 27/28.
     W1 = np.zeros((2, 104)); W1[:, 0] = 1.0
     cases.append(("fp8_weight", "fp8", [W1, np.eye(2), np.diag([3.0, 1.0])], [np.zeros(2)] * 3,
                   [1.0, 1.0 / 448, 1.0 / 448], [3.0, 27.0 / 28]))
-    # FP8 activation rounding: W1 column = [1, 0.5] scales to 448 and 224 (on the grid);
-    # a bias of 0.03 makes the second hidden value 0.53, which s_a = 1/448 maps to
-    # 237.44 -> 240 (grid 224, 240, 256): the next layers see 240/448 = 15/28.
+    # FP8 activation rounding: W1 column = [1, 0.5] scales to 448 and 224 (on the grid;
+    # s_w = 1/448 as above, W2 = I again at s_w = 2^-8); a bias of 0.03 makes the second
+    # hidden value 0.53, which s_a = 1/448 maps to 237.44 -> 240 (grid 224, 240, 256):
+    # the next layers see 240/448 = 15/28.
     # act_scales[0] is ignored, the input bits being exact: 3000 there changes nothing
     # (read as a scale, 1/3000 would round to 0 in E4M3 and zero the first layer).
     W1 = np.zeros((2, 104)); W1[0, 0] = 1.0; W1[1, 0] = 0.5
     cases.append(("fp8_activation", "fp8", [W1, np.eye(2), np.eye(2)],
                   [np.array([0.0, 0.03]), np.zeros(2), np.zeros(2)],
                   [3000.0, 1.0 / 448, 1.0 / 448], [1.0, 15.0 / 28]))
-    # FP8 saturation: W1 column = [3, 0.25] scales to 448 and 37.33 -> 36 (grid 32, 36,
-    # 40), so the hidden values are 3 and 36 * 3/448 = 27/112. With s_a = 1/300 they
-    # map to 900, beyond the format's 448, which saturates to 448, and 72.32 -> 72 (grid
-    # 64, 72, 80): the next layers see 448/300 and 72/300.
+    # FP8 saturation: W1 column = [3, 0.25] has the amax scale 3/448, whose factor into
+    # s_next = 1/300 is 900/448 = 2.01, raised to 4: s_w = 4/300 = 1/75. The column
+    # scales to 225 -> 224 (grid 224, 240) and 18.75 -> 18 (grid 18, 20), so the hidden
+    # values are 224/75 and 18/75. With s_a = 1/300 they map to 896, beyond the format's
+    # 448, which saturates to 448, and 72 (on the grid): the next layers see 448/300 and
+    # 72/300.
     W1 = np.zeros((2, 104)); W1[0, 0] = 3.0; W1[1, 0] = 0.25
     cases.append(("fp8_saturate", "fp8", [W1, np.eye(2), np.eye(2)], [np.zeros(2)] * 3,
                   [1.0, 1.0 / 300, 1.0 / 300], [448.0 / 300, 72.0 / 300]))
+    # FP8 hidden weight scale: W1 column = [3, 0.77] with s_next = 1/100. The amax scale
+    # 3/448 has the factor 300/448 = 0.67 into s_next, raised to 2^0: s_w = 1/100. The
+    # column scales to 300 -> 288 (grid 288, 320) and 77 -> 80 (grid 72, 80), so the
+    # hidden values are 2.88 and 0.8, on the activation grid at s_a = 1/100 (288, 80);
+    # W2 = W3 = I pass them on: logits [2.88, 0.8]. (With the amax scale 3/448 the
+    # column would be 448 and 114.99 -> 112, the second hidden value 0.75, entering the
+    # next layer as 75 -> 72: logit 0.72.)
+    W1 = np.zeros((2, 104)); W1[0, 0] = 3.0; W1[1, 0] = 0.77
+    cases.append(("fp8_hidden_scale", "fp8", [W1, np.eye(2), np.eye(2)], [np.zeros(2)] * 3,
+                  [1.0, 1.0 / 100, 1.0 / 100], [2.88, 0.8]))
     return x, cases
 
 
@@ -353,7 +370,7 @@ def run_quant_case(fwd, x, case):
     return fwd(x, Ws, bs, prec, act_scales=sc)[0]
 
 
-@pytest.mark.parametrize("k", range(5))
+@pytest.mark.parametrize("k", range(6))
 def test_mlp_quantisation_steps_hand_computed(k):
     x, cases = mlp_quant_cases()
     name, prec, Ws, bs, sc, want = cases[k]
@@ -361,6 +378,31 @@ def test_mlp_quantisation_steps_hand_computed(k):
     # the FP32 products of the stated scales (s_a s_w, 1/s) carry relative errors of a
     # few 2^-24; nothing else is inexact
     assert np.allclose(got, want, rtol=1e-6, atol=0), (name, got.tolist(), want)
+
+
+def test_fp8_hidden_weight_scale_closed_form():
+    """The hidden-layer weight scale against its definition: at least the amax scale,
+    below twice it, and s_w s_a / s_next a power of two (up to the fp32 rounding of s_w);
+    it equals the amax scale when that factor is already a power of two."""
+    rng = np.random.default_rng(5)
+    for _ in range(2000):
+        W = rng.normal(0, 10.0 ** rng.uniform(-3, 1), (4, 3))
+        s_a = float(np.float32(10.0 ** rng.uniform(-3, 2)))
+        s_n = float(np.float32(10.0 ** rng.uniform(-3, 2)))
+        s = orc.fp8_weight_scale(W)
+        sw = orc.fp8_hidden_weight_scale(W, s_a, s_n)
+        assert s * (1 - 2.0 ** -23) <= sw < 2 * s * (1 + 2.0 ** -23)
+        k = sw * s_a / s_n
+        assert abs(np.log2(k) - round(np.log2(k))) < 2.0 ** -20
+    # already a power of two: W amax 448 (s = 1), s_a = 1/4, s_next = 1/32 (factor 8)
+    W = np.array([[448.0, -3.0]])
+    assert orc.fp8_hidden_weight_scale(W, 0.25, 1 / 32) == 1.0
+    # amax 448 with s_a = 1/3, s_next = 1/3: factor 1, s_w = 1
+    assert orc.fp8_hidden_weight_scale(W, 1 / 3, 1 / 3) == 1.0
+    # amax 336 (s = 0.75), s_a = s_next: raised to 1
+    assert orc.fp8_hidden_weight_scale(np.array([[336.0]]), 0.5, 0.5) == 1.0
+    # amax 224 (s = 0.5), s_a = 1, s_next = 3: factor 1/6 -> 2^-2, s_w = 3/4
+    assert orc.fp8_hidden_weight_scale(np.array([[224.0]]), 1.0, 3.0) == 0.75
 
 
 def test_mlp_fp32_path_takes_no_rounding():
