@@ -192,3 +192,44 @@ def test_prepared_graphs_serve_every_size_class():
     finally:
         T.tang_server_destroy(srv)
         T.tang_ruleset_destroy(rs)
+
+
+def test_residual_model_batches_beside_graph_batches():
+    """A ruleset with the residual predictor (its batches run eagerly: the staging kernels,
+    then the classification, on the slot's stream) served beside a BF16 ruleset (graph
+    replays), requests of 1 to 8,192 headers alternating between the two: every answer
+    equals the oracle's."""
+    from tests.test_gpu_resnet import _random_model
+
+    torch_cuda()
+    sets = []
+    for k in range(2):
+        rules = synth.make_rules(2000, seed=820 + k)
+        rs = T.tang_ruleset_create(0, rules)
+        C = T.tang_ruleset_num_tuples(rs)
+        if k == 0:
+            Ws, bs = _random_model(C, 2, np.random.default_rng(821))
+            T.tang_model_load_resnet(rs, Ws, bs, "bf16", topk=2)
+        else:
+            Ws, bs = train.random_weights(C, 256, seed=822)
+            T.tang_model_load(rs, Ws, bs, "bf16")
+        sets.append((rules, rs))
+    srv = T.tang_server_create(0, n_streams=3, max_batch=8192, use_graphs=1)
+    try:
+        tags = [T.tang_server_add_ruleset(srv, rs) for _, rs in sets]
+        for t in tags:
+            T.tang_server_prepare(srv, t)
+        reqs = []
+        for q, n in enumerate([1, 33, 100, 4095, 4096, 5000, 8192, 7, 1000, 8191]):
+            tag = q % 2
+            hdr = synth.make_packets(sets[tag][0], n, seed=5000 + q, frac_in=0.8)
+            out = np.full(n, 0xDEADBEEF, dtype=np.uint32)
+            reqs.append((tag, hdr, out, T.tang_server_submit(srv, tags[tag], hdr, out)))
+        for tag, hdr, out, r in reqs:
+            T.tang_server_wait(r, 60_000_000)
+            assert np.array_equal(out, orc.classify(sets[tag][0], hdr)), (tag, len(hdr))
+            T.tang_server_req_free(r)
+    finally:
+        T.tang_server_destroy(srv)
+        for _, rs in sets:
+            T.tang_ruleset_destroy(rs)
