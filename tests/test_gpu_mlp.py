@@ -124,7 +124,9 @@ def test_model_load_validation():
                          ((Ws, bs, "fp8"), {}),                           # no scales
                          ((Ws, bs, "bf16"), {"act_scales": [1, 1, 1]}),   # scales not FP8
                          ((Ws, bs, "fp32"), {"topk": 5}),
-                         ((Ws, bs, "fp8"), {"act_scales": [1, 0.0, 1]})]:
+                         ((Ws, bs, "fp8"), {"act_scales": [1, 0.0, 1]}),
+                         # a requantisation factor beyond 2^100 between the hidden layers
+                         ((Ws, bs, "fp8"), {"act_scales": [1, 1e30, 1e-8]})]:
             with pytest.raises(T.TangError) as e:
                 T.tang_model_load(rs, *args, **kw)
             assert e.value.name == "EINVAL"
