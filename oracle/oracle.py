@@ -20,8 +20,9 @@ Contents, each written from the passage it cites:
 * ``mlp_forward``         -- the plain MLP of Sec. 6.1 without residual blocks
                              (FC -> ReLU -> FC -> ReLU -> FC), in float64, with the
                              BF16 / FP8 quantisation steps emulated on the inputs of
-                             each layer; ``topk`` picks predicted tuples (argmax of
-                             Sec. 6.1, ties to the lower index).
+                             each layer (FP8 weight scales: ``fp8_weight_scale``,
+                             ``fp8_hidden_weight_scale``); ``topk`` picks predicted
+                             tuples (argmax of Sec. 6.1, ties to the lower index).
 * ``segments`` / ``resnet_forward`` -- the paper's own model input and network
                              (Sec. 6.2 input format, Sec. 6.1 with residual blocks,
                              Eq. 1, sizes of Sec. 7.1): seven 16-bit header chunks as
