@@ -332,6 +332,15 @@ typedef struct tang_server_cfg_s {
 typedef struct tang_server_s tang_server_t;
 typedef struct tang_req_s tang_req_t;
 
+/*
+ * Start a serving loop on HIP device `device` (one host thread, n_streams stream slots).
+ * cfg may be NULL; zero fields take defaults: 4 streams, max_batch 65536, in-flight
+ * packets n_streams x max_batch, staging budget that many packets' bytes (20 each). Each
+ * slot holds 16 (max_batch + 1) + 4 max_batch bytes of pinned, coherent host staging and
+ * the same of device memory (through the allocator of tang_set_allocator if one is set),
+ * until tang_server_destroy. EINVAL on a bad device or configuration (n_streams above 8,
+ * max_batch not a power of two of at least 32), EDEVICE without a device.
+ */
 int tang_server_create(int device, const tang_server_cfg_t* cfg, tang_server_t** out);
 /*
  * Register a ruleset (same device); *tag identifies it in submits. May be called while
