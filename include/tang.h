@@ -170,14 +170,18 @@ int tang_ruleset_export(const tang_ruleset_t* rs, tang_rule_t* out, size_t cap, 
  * pointer to dims[l+1] x dims[l] floats, row-major [out][in] (PyTorch
  * nn.Linear.weight); b[l] to dims[l+1] floats.
  * precision: FP32 (weights as given), BF16 (weights and each layer's input rounded to
- * bfloat16, nearest-even), FP8 (OCP E4M3, per-layer weight scale amax|W|/448 and
- * static per-layer activation scales act_scales[l] for l >= 1, act_scales[0] ignored
- * since the input bits are exact; inputs saturate at +-448). Accumulation is FP32 and
- * biases stay FP32 in every precision. act_scales must be NULL unless precision is FP8.
+ * bfloat16, nearest-even), FP8 (OCP E4M3 with static per-layer activation scales
+ * act_scales[l] for l >= 1, act_scales[0] ignored since the input bits are exact;
+ * inputs saturate at +-448; the output layer's weight scale is amax|W|/448, a hidden
+ * layer's that scale raised by a factor in [1, 2) until s_w * act_scales[l] /
+ * act_scales[l + 1] is a power of two, 2^e, so the layer's output is requantised by an
+ * exact scaling; EINVAL if |e| > 100). Accumulation is FP32 and biases stay FP32 in every
+ * precision. act_scales must be NULL unless precision is FP8.
  * Replaces any previously loaded model. Without a model, classify probes all tuples.
  */
 int tang_model_load(tang_ruleset_t* rs, const tang_mlp_desc_t* desc, const float* const* W,
                     const float* const* b, tang_precision_t precision, const float* act_scales);
+/* Drop the loaded model (of either kind); classify then probes every tuple. */
 int tang_model_unload(tang_ruleset_t* rs);
 
 /*
