@@ -337,7 +337,8 @@ typedef struct tang_server_s tang_server_t;
 typedef struct tang_req_s tang_req_t;
 
 /*
- * Start a serving loop on HIP device `device` (one host thread, n_streams stream slots).
+ * Start a serving loop on HIP device `device` (one loop thread, three helper threads for
+ * the host copies of large batches, n_streams stream slots).
  * cfg may be NULL; zero fields take defaults: 4 streams, max_batch 65536, in-flight
  * packets n_streams x max_batch, staging budget that many packets' bytes (20 each). Each
  * slot holds 16 (max_batch + 1) + 4 max_batch bytes of pinned, coherent host staging and

@@ -21,7 +21,10 @@
 // requests as they arrive) and launches each once on an empty batch, so that requests
 // pay neither for graph captures nor for first launches.
 // Requests that arrive while others are on the GPU are admitted as slots and budget
-// free up, so batches of different requests and rulesets overlap on the device.
+// free up, so batches of different requests and rulesets overlap on the device. The host
+// copies of a large batch (its headers into the staging, its rule ids back out) are spread
+// over the loop thread and three helper threads.
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -74,6 +77,91 @@ struct StreamSlot {
 struct GraphEntry {
     uint64_t version = ~0ull;
     hipGraphExec_t exec = nullptr;
+};
+
+// Host copies of a batch (headers into the pinned staging, rule ids out of it) spread over
+// the loop thread and a few helper threads: one thread's memcpy moves a large batch
+// several times slower than the GPU classifies it. run() returns once every chunk is
+// copied and every helper has let go of the chunk list.
+struct CopyChunk {
+    void* dst;
+    const void* src;
+    size_t n;
+};
+static constexpr size_t kChunkBytes = 256u << 10;
+// batches below this many headers (single requests included: they are at most 65,536
+// headers in the serving workload) copy on the loop thread alone, without waking helpers
+static constexpr size_t kPoolMinHeaders = 131072;
+static constexpr unsigned kCopyHelpers = 3;
+
+class CopyPool {
+  public:
+    explicit CopyPool(unsigned helpers) {
+        for (unsigned k = 0; k < helpers; ++k) th_.emplace_back([this] { work(); });
+    }
+    ~CopyPool() {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    // Appends the copy of n bytes, cut into chunks.
+    static void add(std::vector<CopyChunk>& c, void* dst, const void* src, size_t n) {
+        for (size_t off = 0; off < n; off += kChunkBytes)
+            c.push_back(CopyChunk{static_cast<char*>(dst) + off, static_cast<const char*>(src) + off,
+                                  std::min(kChunkBytes, n - off)});
+    }
+    void run(const std::vector<CopyChunk>& c, bool spread) {
+        if (th_.empty() || !spread) {
+            for (const auto& x : c) std::memcpy(x.dst, x.src, x.n);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            job_ = &c;
+            next_.store(0);
+            busy_ = th_.size();
+            ++gen_;
+        }
+        cv_.notify_all();
+        grab(c);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_cv_.wait(lk, [&] { return busy_ == 0; });
+        job_ = nullptr;
+    }
+
+  private:
+    void grab(const std::vector<CopyChunk>& c) {
+        for (size_t k; (k = next_.fetch_add(1)) < c.size();) std::memcpy(c[k].dst, c[k].src, c[k].n);
+    }
+    void work() {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::vector<CopyChunk>* j = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+                j = job_;
+            }
+            grab(*j);
+            {
+                std::lock_guard<std::mutex> g(mu_);
+                if (--busy_ == 0) done_cv_.notify_all();
+            }
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    const std::vector<CopyChunk>* job_ = nullptr;
+    std::atomic<size_t> next_{0};
+    size_t busy_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
 };
 
 constexpr uint32_t kStageThreads = 256;
@@ -139,6 +227,8 @@ struct tang_server_s {
     std::vector<char> warmed;
     std::vector<char> prepared;   // 0 not asked, 1 asked, 2 every (class, slot) graph recorded
     std::condition_variable prepared_cv;
+    std::unique_ptr<CopyPool> copies;   // used by the loop thread only
+    std::vector<CopyChunk> chunks;
 
     void loop();
     void finish(StreamSlot& s, int status);
@@ -216,11 +306,13 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, tang_ruleset_t* rs, bool wa
     s.offs.clear();
     s.total = total;
     size_t off = 0;
+    chunks.clear();
     for (auto& r : batch) {
         s.offs.push_back(off);
-        std::memcpy(s.h_hdr() + off, r->hdr, r->n * sizeof(tang_header_t));
+        CopyPool::add(chunks, s.h_hdr() + off, r->hdr, r->n * sizeof(tang_header_t));
         off += r->n;
     }
+    copies->run(chunks, total >= kPoolMinHeaders);
     size_t cls = 32;
     while (cls < total) cls <<= 1;
     const uint32_t live = (uint32_t)total;   // total <= max_batch, a 32-bit value
@@ -287,10 +379,15 @@ bool tang_server_s::prepare(uint32_t tag, tang_ruleset_t* rs, bool warm) {
 }
 
 void tang_server_s::finish(StreamSlot& s, int status) {
+    if (status == TANG_OK) {
+        chunks.clear();
+        for (size_t k = 0; k < s.reqs.size(); ++k)
+            CopyPool::add(chunks, s.reqs[k]->out, s.h_out + s.offs[k], s.reqs[k]->n * sizeof(uint32_t));
+        copies->run(chunks, s.total >= kPoolMinHeaders);
+    }
     const uint64_t t = now_ns();
     for (size_t k = 0; k < s.reqs.size(); ++k) {
         auto& r = s.reqs[k];
-        if (status == TANG_OK) std::memcpy(r->out, s.h_out + s.offs[k], r->n * sizeof(uint32_t));
         {
             std::lock_guard<std::mutex> g(r->mu);
             r->t_done = t;
@@ -451,7 +548,13 @@ int tang_server_create(int device, const tang_server_cfg_t* cfg, tang_server_t**
             free_server(srv);
             return hip_fail(e, "tang_server_create");
         }
-        srv->th = std::thread([srv] { srv->loop(); });
+        try {
+            srv->copies.reset(new CopyPool(kCopyHelpers));
+            srv->th = std::thread([srv] { srv->loop(); });
+        } catch (...) {
+            free_server(srv);
+            return fail(TANG_ENOMEM, "could not start the serving threads");
+        }
         *out = srv;
         return TANG_OK;
     } catch (const std::bad_alloc&) {
