@@ -338,7 +338,8 @@ typedef struct tang_req_s tang_req_t;
 
 /*
  * Start a serving loop on HIP device `device` (one loop thread, three helper threads for
- * the host copies of large batches, n_streams stream slots).
+ * the host copies of large batches, n_streams stream slots with one issuing thread each
+ * for the batches that move through the copy engines).
  * cfg may be NULL; zero fields take defaults: 4 streams, max_batch 65536, in-flight
  * packets n_streams x max_batch, staging budget that many packets' bytes (20 each). Each
  * slot holds 16 (max_batch + 1) + 4 max_batch bytes of pinned, coherent host staging and

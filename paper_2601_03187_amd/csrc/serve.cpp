@@ -7,11 +7,13 @@
 // and staging bytes in flight stay within the configured limits, writes their headers
 // into the slot's pinned staging, replays the HIP graph captured for (ruleset, batch size
 // class, slot) and records an event. Completed slots hand results to their requests.
-// The graph moves the batch itself: a first kernel pulls the headers from the pinned
-// staging into device memory, a last one pushes the rule ids back, so that a batch costs
-// one graph launch and no runtime copy (asynchronous runtime copies have been seen to
-// hold the calling thread for 6-11 ms now and then, which stalled admission for every
-// slot).
+// Below 131,072 headers the graph moves the batch itself: a first kernel pulls the
+// headers from the pinned staging into device memory, a last one pushes the rule ids
+// back, so that a batch costs one graph launch and no runtime copy (asynchronous runtime
+// copies have been seen to hold the calling thread for 6-11 ms now and then, which
+// stalled admission for every slot when the loop issued them). Larger batches go through
+// the copy engines, faster than kernel reads of host memory, issued around the graph by
+// the slot's own thread (SlotIssuer), so that a held call delays only that slot.
 // A graph is recorded for the largest batch of its size class (a power of two); the
 // batch's real header count travels with its headers (the first 16 bytes of the slot's
 // staging) and the kernels read it from there, so a batch
@@ -69,6 +71,7 @@ struct StreamSlot {
     tang_header_t* d_hdr() const { return d_buf + 1; }
     const uint32_t* d_live() const { return reinterpret_cast<const uint32_t*>(d_buf); }
     bool busy = false;
+    bool issued_by_slot = false;   // the batch was posted to the slot's issuer thread
     size_t total = 0;
     std::vector<std::shared_ptr<ReqState>> reqs;
     std::vector<size_t> offs;
@@ -164,6 +167,74 @@ class CopyPool {
     bool stop_ = false;
 };
 
+// Batches of the large size classes move through the copy engines (hipMemcpyAsync: about
+// 1.3x the rate of the staging kernels' reads of host memory). A runtime copy call has been
+// seen to hold its calling thread for 6-11 ms now and then, so these batches are issued by
+// the slot's own thread: a held call delays that slot's batch, not the loop's admissions.
+// The loop posts a batch (its staging is written, its graph recorded) and, once issued()
+// turns true, polls the slot's event as for any batch.
+class SlotIssuer {
+  public:
+    SlotIssuer(int device, StreamSlot* s) : s_(s), th_([this, device] { work(device); }) {}
+    ~SlotIssuer() {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            quit_ = true;
+        }
+        cv_.notify_all();
+        th_.join();
+    }
+    void post(hipGraphExec_t exec, size_t total) {
+        issued_.store(false, std::memory_order_relaxed);
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            exec_ = exec;
+            total_ = total;
+            job_ = true;
+        }
+        cv_.notify_one();
+    }
+    bool issued() const { return issued_.load(std::memory_order_acquire); }
+    int status() const { return status_; }   // valid once issued()
+
+  private:
+    void work(int device) {
+        (void)hipSetDevice(device);
+        for (;;) {
+            hipGraphExec_t exec;
+            size_t total;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return quit_ || job_; });
+                if (quit_) return;
+                job_ = false;
+                exec = exec_;
+                total = total_;
+            }
+            StreamSlot& s = *s_;
+            hipError_t e = hipMemcpyAsync(s.d_buf, s.h_buf, (total + 1) * sizeof(tang_header_t),
+                                          hipMemcpyHostToDevice, s.stream);
+            if (e == hipSuccess) e = hipGraphLaunch(exec, s.stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(s.h_out, s.d_out, total * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                   s.stream);
+            if (e == hipSuccess) e = hipEventRecord(s.ev, s.stream);
+            status_ = e == hipSuccess ? TANG_OK : TANG_EDEVICE;
+            issued_.store(true, std::memory_order_release);
+        }
+    }
+    StreamSlot* s_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    bool job_ = false, quit_ = false;
+    hipGraphExec_t exec_ = nullptr;
+    size_t total_ = 0;
+    int status_ = TANG_OK;
+    std::atomic<bool> issued_{true};
+    std::thread th_;
+};
+static constexpr uint64_t kCopyEngineClass = 1u << 17;   // size classes that use SlotIssuer
+
 constexpr uint32_t kStageThreads = 256;
 constexpr uint32_t kInPerThread = 4;    // headers per thread of k_stage_in
 constexpr uint32_t kOutPerThread = 4;   // rule ids per thread of k_stage_out
@@ -229,6 +300,7 @@ struct tang_server_s {
     std::condition_variable prepared_cv;
     std::unique_ptr<CopyPool> copies;   // used by the loop thread only
     std::vector<CopyChunk> chunks;
+    std::vector<std::unique_ptr<SlotIssuer>> issuers;   // one per slot
 
     void loop();
     void finish(StreamSlot& s, int status);
@@ -237,7 +309,7 @@ struct tang_server_s {
     int graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uint32_t slot_idx,
                   hipGraphExec_t* out);
     bool prepare(uint32_t tag, tang_ruleset_t* rs, bool warm);
-    int run_batch(tang_ruleset_t* rs, StreamSlot& s, size_t cap, bool live_count);
+    int run_batch(tang_ruleset_t* rs, StreamSlot& s, size_t cap, bool live_count, bool staged = true);
 };
 
 using namespace tang;
@@ -260,7 +332,7 @@ int tang_server_s::graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uin
     }
     StreamSlot& s = slots[si];
     TANG_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeRelaxed));
-    int rc = run_batch(rs, s, cls, true);
+    int rc = run_batch(rs, s, cls, true, cls < kCopyEngineClass);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s.stream, &graph);
     if (rc) {
@@ -283,7 +355,10 @@ int tang_server_s::graph_for(uint32_t tag, tang_ruleset_t* rs, uint32_t cls, uin
 // classification, the rule ids out. With `live_count` the kernels take the batch's size
 // from the staging (launches sized for `cap`, as a graph records them); without it `cap`
 // is the batch's size.
-int tang_server_s::run_batch(tang_ruleset_t* rs, StreamSlot& s, size_t cap, bool live_count) {
+int tang_server_s::run_batch(tang_ruleset_t* rs, StreamSlot& s, size_t cap, bool live_count,
+                             bool staged) {
+    // a copy-engine batch's graph is the classification alone (its copies are issued around it)
+    if (!staged) return classify_async(rs, s.d_hdr(), s.d_out, cap, s.stream, nullptr, false, s.d_live());
     const uint32_t c = (uint32_t)cap;   // cap <= max_batch, a 32-bit value
     constexpr uint32_t in_blk = kInPerThread * kStageThreads, out_blk = kOutPerThread * kStageThreads;
     hipLaunchKernelGGL(k_stage_in, dim3((c + in_blk - 1) / in_blk), dim3(kStageThreads),
@@ -329,6 +404,12 @@ int tang_server_s::launch(uint32_t si, uint32_t tag, tang_ruleset_t* rs, bool wa
         hipGraphExec_t exec = nullptr;
         int rc = graph_for(tag, rs, (uint32_t)cls, si, &exec);
         if (rc) return rc;
+        if (cls >= kCopyEngineClass) {
+            issuers[si]->post(exec, total);
+            s.issued_by_slot = true;
+            s.busy = true;
+            return TANG_OK;
+        }
         TANG_HIP(hipGraphLaunch(exec, s.stream));
     } else {
         int rc = run_batch(rs, s, total, false);
@@ -369,7 +450,9 @@ bool tang_server_s::prepare(uint32_t tag, tang_ruleset_t* rs, bool warm) {
         }
         StreamSlot& s = slots[si];
         s.h_buf[0] = tang_header_t{};
-        hipError_t e = hipSuccess;
+        // the copy-engine classes' graphs read the live count from device memory
+        hipError_t e = hipMemcpyAsync(s.d_buf, s.h_buf, sizeof(tang_header_t), hipMemcpyHostToDevice,
+                                      s.stream);
         for (size_t k = 0; k < execs.size() && e == hipSuccess; ++k)
             e = hipGraphLaunch(execs[k], s.stream);
         (void)hipStreamSynchronize(s.stream);
@@ -403,6 +486,7 @@ void tang_server_s::finish(StreamSlot& s, int status) {
     }
     s.reqs.clear();
     s.busy = false;
+    s.issued_by_slot = false;
     s.total = 0;
 }
 
@@ -410,8 +494,17 @@ void tang_server_s::loop() {
     (void)hipSetDevice(device);  // the ordinal was checked at creation
     for (;;) {
         bool progressed = false;
-        for (auto& s : slots) {
+        for (uint32_t si = 0; si < slots.size(); ++si) {
+            StreamSlot& s = slots[si];
             if (!s.busy) continue;
+            if (s.issued_by_slot) {
+                if (!issuers[si]->issued()) continue;   // its event is not recorded yet
+                if (issuers[si]->status() != TANG_OK) {
+                    finish(s, issuers[si]->status());
+                    progressed = true;
+                    continue;
+                }
+            }
             hipError_t q = hipEventQuery(s.ev);
             if (q == hipSuccess) {
                 finish(s, TANG_OK);
@@ -491,6 +584,7 @@ void tang_server_s::loop() {
 }
 
 static void free_server(tang_server_t* srv) {
+    srv->issuers.clear();   // joins the issuer threads (idle: the loop has drained every slot)
     (void)hipSetDevice(srv->device);
     for (auto& kv : srv->graphs)
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
@@ -550,6 +644,7 @@ int tang_server_create(int device, const tang_server_cfg_t* cfg, tang_server_t**
         }
         try {
             srv->copies.reset(new CopyPool(kCopyHelpers));
+            for (auto& sl : srv->slots) srv->issuers.emplace_back(new SlotIssuer(device, &sl));
             srv->th = std::thread([srv] { srv->loop(); });
         } catch (...) {
             free_server(srv);

@@ -233,3 +233,37 @@ def test_residual_model_batches_beside_graph_batches():
         T.tang_server_destroy(srv)
         for _, rs in sets:
             T.tang_ruleset_destroy(rs)
+
+
+def test_copy_engine_batches_beside_staged_ones():
+    """Batches of 131,072 headers and more move through the copy engines, issued by the
+    slot's own thread; smaller ones through the staging kernels. A burst that merges into
+    batches of both kinds (a 200,000-header request, 65,536-header requests that merge up
+    to 262,144, small ones), before and after a new model: every answer equals the
+    oracle's."""
+    torch_cuda()
+    rules = synth.make_rules(3000, seed=830)
+    rs = T.tang_ruleset_create(0, rules)
+    C = T.tang_ruleset_num_tuples(rs)
+    Ws, bs = train.random_weights(C, 256, seed=831)
+    T.tang_model_load(rs, Ws, bs, "bf16")
+    srv = T.tang_server_create(0, n_streams=2, max_batch=262144, use_graphs=1)
+    try:
+        tag = T.tang_server_add_ruleset(srv, rs)
+        T.tang_server_prepare(srv, tag)
+        sizes = [200_000, 65_536, 65_536, 65_536, 65_536, 33, 131_072, 70_000, 1, 65_536, 4_096]
+        for round_ in range(2):
+            reqs = []
+            for q, n in enumerate(sizes):
+                hdr = synth.make_packets(rules, n, seed=6000 + 100 * round_ + q, frac_in=0.8)
+                out = np.full(n, 0xDEADBEEF, dtype=np.uint32)
+                reqs.append((hdr, out, T.tang_server_submit(srv, tag, hdr, out)))
+            for hdr, out, r in reqs:
+                T.tang_server_wait(r, 60_000_000)
+                assert np.array_equal(out, orc.classify(rules, hdr)), (round_, len(hdr))
+                T.tang_server_req_free(r)
+            Wf, bf = train.random_weights(C, 256, seed=832)
+            T.tang_model_load(rs, Wf, bf, "bf16", topk=2)
+    finally:
+        T.tang_server_destroy(srv)
+        T.tang_ruleset_destroy(rs)
