@@ -981,7 +981,7 @@ def bench_serving(args):
     log("[bench c5] rulesets ready")
     # batches merge requests up to 262,144 headers (four of the largest requests): the
     # fixed cost of a batch (launches, copies, a partly filled GPU) then spreads over more
-    # headers when requests queue up (saturation 740 Mpps with 65,536, 1,350 with 262,144,
+    # headers when requests queue up (saturation 740 Mpps with 65,536, about 1,900 with 262,144,
     # measured); at low load a batch is a single request either way
     srv = T.tang_server_create(0, n_streams=4, max_batch=262144, use_graphs=1)
     tags = [T.tang_server_add_ruleset(srv, rs) for _, rs, _ in sets]
