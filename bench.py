@@ -959,7 +959,8 @@ def print_updates(res):
 def bench_serving(args):
     """c5: three device-resident rulesets (10k, 100k, 512k rules, BF16 predictors) behind
     the serving loop; requests of log-uniform size 32..65,536 with a uniform ruleset tag.
-    First a burst measures saturation; then Poisson arrivals at 25/50/75/90% of it report
+    After a warm-up burst, two bursts measure saturation (the faster one counts); then
+    Poisson arrivals at 25/50/75/90% of it report
     p50/p99 request latency (submit -> results on the host) and delivered Mpps. A sample of
     requests is checked against the same headers classified alone."""
     import numpy as np
@@ -1017,7 +1018,11 @@ def bench_serving(args):
                       "offered_req_per_s": rate, "submit_s": time.perf_counter() - t0}
 
     run(args.requests, 0, seed=1)  # warm-up
-    reqs, sat = run(args.requests, 0, seed=2)
+    # two saturation bursts: a runtime copy call that holds for several milliseconds (seen
+    # a few times per process) can land in one; the faster burst sets the load levels, and
+    # both are reported
+    sats = [run(args.requests, 0, seed=2)[1], run(args.requests, 0, seed=3)[1]]
+    sat = max(sats, key=lambda r: r["mpps"])
     mean_size = sat["packets"] / sat["requests"]
     sat_rate = sat["mpps"] * 1e6 / mean_size
     levels = {}
@@ -1033,7 +1038,7 @@ def bench_serving(args):
     res = {"workload": "c5_serving: rulesets of 10k/100k/512k rules, Poisson requests, sizes "
                        "log-uniform 32..65536, 4 streams, batches up to 262,144 headers, HIP graphs, "
                        "BF16 predictors",
-           "saturation": sat, "loads": levels,
+           "saturation": sat, "saturation_bursts_mpps": [r["mpps"] for r in sats], "loads": levels,
            "alone_vs_mix": {"requests_checked": 50, "mismatches": bad}}
     T.tang_server_destroy(srv)
     for _, rs, _ in sets:

@@ -7,7 +7,7 @@
 // and staging bytes in flight stay within the configured limits, writes their headers
 // into the slot's pinned staging, replays the HIP graph captured for (ruleset, batch size
 // class, slot) and records an event. Completed slots hand results to their requests.
-// Below 131,072 headers the graph moves the batch itself: a first kernel pulls the
+// Up to 65,536 headers the graph moves the batch itself: a first kernel pulls the
 // headers from the pinned staging into device memory, a last one pushes the rule ids
 // back, so that a batch costs one graph launch and no runtime copy (asynchronous runtime
 // copies have been seen to hold the calling thread for 6-11 ms now and then, which
@@ -233,7 +233,9 @@ class SlotIssuer {
     std::atomic<bool> issued_{true};
     std::thread th_;
 };
-static constexpr uint64_t kCopyEngineClass = 1u << 17;   // size classes that use SlotIssuer
+// size classes that use SlotIssuer: batches of more than 65,536 headers, which only form
+// when requests queue up and merge
+static constexpr uint64_t kCopyEngineClass = 1u << 17;
 
 constexpr uint32_t kStageThreads = 256;
 constexpr uint32_t kInPerThread = 4;    // headers per thread of k_stage_in
@@ -455,6 +457,14 @@ bool tang_server_s::prepare(uint32_t tag, tang_ruleset_t* rs, bool warm) {
                                       s.stream);
         for (size_t k = 0; k < execs.size() && e == hipSuccess; ++k)
             e = hipGraphLaunch(execs[k], s.stream);
+        // one full-size copy each way on the slot's stream, so that the copy engines' first
+        // use (which can take milliseconds) falls here rather than on a request
+        if (e == hipSuccess && cfg.max_batch >= kCopyEngineClass)
+            e = hipMemcpyAsync(s.d_buf, s.h_buf, ((size_t)cfg.max_batch + 1) * sizeof(tang_header_t),
+                               hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess && cfg.max_batch >= kCopyEngineClass)
+            e = hipMemcpyAsync(s.h_out, s.d_out, (size_t)cfg.max_batch * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, s.stream);
         (void)hipStreamSynchronize(s.stream);
         if (e != hipSuccess) return true;
     }

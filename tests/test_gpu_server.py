@@ -236,7 +236,7 @@ def test_residual_model_batches_beside_graph_batches():
 
 
 def test_copy_engine_batches_beside_staged_ones():
-    """Batches of 131,072 headers and more move through the copy engines, issued by the
+    """Batches of more than 65,536 headers move through the copy engines, issued by the
     slot's own thread; smaller ones through the staging kernels. A burst that merges into
     batches of both kinds (a 200,000-header request, 65,536-header requests that merge up
     to 262,144, small ones), before and after a new model: every answer equals the
