@@ -170,7 +170,9 @@ class CopyPool {
 // Batches of the large size classes move through the copy engines (hipMemcpyAsync: about
 // 1.3x the rate of the staging kernels' reads of host memory). A runtime copy call has been
 // seen to hold its calling thread for 6-11 ms now and then, so these batches are issued by
-// the slot's own thread: a held call delays that slot's batch, not the loop's admissions.
+// the slot's own thread and a held call never blocks the loop thread itself (other HIP
+// work can still wait behind it inside the runtime: once, a whole burst came out about
+// 8 ms late).
 // The loop posts a batch (its staging is written, its graph recorded) and, once issued()
 // turns true, polls the slot's event as for any batch.
 class SlotIssuer {
