@@ -381,7 +381,11 @@ def main():
                             "bytes_per_pkt": head["search_bytes_per_pkt"],
                             "overhead_bytes_per_pkt": head["search_overhead_bytes_per_pkt"],
                             "overhead": "bucket-filter blocks (8 B each) and the predictor's "
-                                        "candidate word (4 B), not counted in bytes_per_pkt"}}
+                                        "candidate word (4 B), not counted in bytes_per_pkt",
+                            "what_binds": "issue, not HBM: the whole-batch search keeps the "
+                                          "texture data units about 97% busy and issues VALU "
+                                          "in about 93% of its cycles (derived shares in "
+                                          "profiles/k_classify_c3_512k_zipf_16m.txt)"}}
     tr = measured_traffic("k_classify", wl)
     if tr:
         other["k_classify"]["traffic_over_algorithmic"] = tr / (head["search_bytes_per_pkt"] * n)
