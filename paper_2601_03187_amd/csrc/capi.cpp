@@ -372,15 +372,24 @@ static int classify_chunked(tang_ruleset_t* rs, const tang_header_t* d_hdr, uint
     std::unique_lock<std::mutex> lk(rs->pipe_mu, std::try_to_lock);
     if (!lk.owns_lock()) return TANG_OK;
     if (!rs->pipe_stream) TANG_HIP(hipStreamCreateWithFlags(&rs->pipe_stream, hipStreamNonBlocking));
-    const size_t K = (n + kPipeChunk - 1) / kPipeChunk;
+    // A half chunk first and last (the first chunk's predictor and the last chunk's search
+    // run with nothing beside them), the rest in equal parts of at most kPipeChunk;
+    // n >= 2 kPipeChunk here.
+    const size_t E = kPipeChunk / 2, M = n - 2 * E;
+    const size_t q = (M + kPipeChunk - 1) / kPipeChunk, part = (M + q - 1) / q;
+    std::vector<size_t> sz{E};
+    for (size_t left = M; left > 0; left -= std::min(part, left)) sz.push_back(std::min(part, left));
+    sz.push_back(E);
+    const size_t K = sz.size();
     while (rs->pipe_events.size() < K + 1) {
         hipEvent_t e = nullptr;
         TANG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         rs->pipe_events.push_back(e);
     }
     const int kcand = rs->model.topk;
-    for (size_t k = 0; k < K; ++k) {
-        const size_t base = k * kPipeChunk, m = std::min(kPipeChunk, n - base);
+    size_t base = 0;
+    for (size_t k = 0; k < K; base += sz[k], ++k) {
+        const size_t m = sz[k];
         TANG_HIP(launch_mlp(rs, d_hdr + base, m, out + base, nullptr, nullptr, s, true));
         TANG_HIP(hipEventRecord(rs->pipe_events[k], s));
         TANG_HIP(hipStreamWaitEvent(rs->pipe_stream, rs->pipe_events[k], 0));

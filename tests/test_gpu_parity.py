@@ -178,7 +178,8 @@ def test_c2_64k_rules_mix(prec):
 def test_chunked_two_stream_classify_equals_oracle():
     """A batch of at least two 2^21-header chunks with a model is classified chunk by
     chunk, the searches on the ruleset's own stream: the 1,000,000 headers of the 64k
-    configuration tiled to 4,194,304 + 777 (three chunks, the last ragged), every answer
+    configuration tiled to 4,194,304 + 777 (a half chunk first and last, two ragged
+    chunks between), every answer
     compared with the oracle's, on a side stream, twice in a row, for top-1 and top-2."""
     torch = torch_cuda()
     rules, hdr, want = _c2_inputs()
