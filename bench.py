@@ -997,12 +997,17 @@ def bench_serving(args):
         t_arr, sizes, tg = synth.make_requests(n_req, len(sets), seed=seed, rate_per_s=rate or 1.0)
         rng = np.random.default_rng(seed)
         # requests (header slices and result buffers) are made before the clock starts, so
-        # the submitting loop does nothing but wait for arrival times and submit
+        # the submitting loop does nothing but wait for arrival times and submit; the result
+        # buffers are written once here, since the first write into a fresh buffer page
+        # faults, and those faults would land on the serving loop's result copies (about 17k
+        # pages per level: enough to slow a whole level)
         work = []
         for q in range(n_req):
             pool = sets[tg[q]][2]
             off = int(rng.integers(0, len(pool) - sizes[q]))
-            work.append((int(tg[q]), pool[off: off + sizes[q]], np.empty(sizes[q], dtype=np.uint32)))
+            work.append((int(tg[q]), pool[off: off + sizes[q]], np.zeros(sizes[q], dtype=np.uint32)))
+        for _, _, out in work:
+            out.fill(0xFFFFFFFF)
         reqs = []
         t0 = time.perf_counter()
         for q, (tag, hdr, out) in enumerate(work):
