@@ -368,7 +368,9 @@ int tang_server_add_ruleset(tang_server_t* srv, tang_ruleset_t* rs, uint32_t* ta
 int tang_server_prepare(tang_server_t* srv, uint32_t tag);
 /*
  * Submit n host headers for ruleset `tag`; results go to host array out[n] when the
- * request completes. hdr and out must stay valid until then. EBUSY if the request can
+ * request completes. hdr and out must stay valid until then. The serving loop's threads
+ * write out: a buffer whose pages were already touched (reused, or written once) keeps
+ * first-touch page faults out of the loop. EBUSY if the request can
  * never be admitted (larger than the limits), EINVAL on a bad tag.
  */
 int tang_server_submit(tang_server_t* srv, uint32_t tag, const tang_header_t* hdr, size_t n,
